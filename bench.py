@@ -1,0 +1,138 @@
+"""Benchmark of the lattice Dyson solve on one MI355X.
+
+One step = the whole hot path on the 16x16 trapped lattice with a 144-point
+contour (all 256 source sites in one column block, i.e. every G_ij):
+sigma_build -> dyson_iterate (FP64, to a relative increment of 1e-12) ->
+local_observables.  Inputs (trap potential, U(t), J(t)) are resident on the
+GPU before the timed region.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload N] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1309_5994_amd import workloads as W          # noqa: E402
+
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (MFMA = vector)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", type=int, default=2, help="named workload 1..5")
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, flops_per_source):
+    """Time the oracle (block-tridiagonal direct solve) for one source site of the
+    same workload on the host cores; express it in Dyson-sweep TFLOP/s, i.e. the
+    algorithmic flops the GPU path spends on that source divided by the oracle's
+    time to produce the same columns."""
+    import oracle as O
+    threads = os.cpu_count() or 1
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.t_min)
+    t0 = time.perf_counter()
+    eps = O.site_levels(wl.V, wl.U, wl.mu)
+    S = np.stack([O.atomic_gf(e, wl.U, c) for e in eps])
+    src = [(wl.Lx // 2) * wl.Ly + wl.Ly // 2]
+    O.dyson_columns_blocktri(S, wl.Lx, wl.Ly, wl.J, c, src)
+    secs = time.perf_counter() - t0
+    return {"value": flops_per_source * len(src) / secs / 1e12, "unit": "TFLOP/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"{wl.name}: exact columns of 1 source site (centre) by block-tridiagonal "
+                      f"LU (scipy/OpenBLAS), {secs:.1f} s incl. S build; value = GPU-path "
+                      f"algorithmic flops for that source / oracle time",
+            "seconds": secs}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(column blocks shard over GPUs, see DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+    from paper_1309_5994_amd import scdyson as B
+
+    dev = torch.device("cuda:0")
+    wl = W.config(args.workload)
+    prob = B.problem_from_workload(wl)
+    V = torch.tensor(wl.V, dtype=torch.float64, device=dev)
+    U = torch.tensor(wl.U, dtype=torch.float64, device=dev)
+    J = torch.tensor(wl.J, dtype=torch.float64, device=dev)
+    src = list(range(wl.n_r))
+    block = wl.block_sites
+    n_t = wl.n_t
+    S = torch.empty((wl.n_r, n_t, n_t), dtype=torch.complex128, device=dev)
+    outs = {"G_loc": torch.empty((wl.n_r, n_t, n_t), dtype=torch.complex128, device=dev),
+            "G_nn": torch.empty((wl.n_r, 4, n_t, n_t), dtype=torch.complex128, device=dev)}
+    ws = torch.empty(B.workspace_bytes(prob, len(src), block), dtype=torch.uint8, device=dev)
+
+    def step():
+        B.sigma_build(prob, V, U, S)
+        r = B.dyson_iterate(prob, S, J, src, block_sites=block, tol=args.tol, max_iter=1000,
+                            ws=ws, out=outs)
+        n, ek = B.local_observables(prob, r["G_loc"], r["G_nn"], J)
+        return r["stats"], n
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st, n = step()
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    flops = sum(s["gemm_flops"] for s in stats)
+    kern_s = sum(s["sweep_kernel_seconds"] for s in stats)
+    launches = sum(s["sweep_launches"] for s in stats)
+    value = flops / elapsed / 1e12
+    achieved = flops / kern_s / 1e12
+    rec = {
+        "metric": "Dyson-iteration TFLOP/s (FP64) to converged G",
+        "value": round(value, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "lattice": f"{wl.Lx}x{wl.Ly}", "n_t": n_t,
+                   "sources": len(src), "block_sites": block, "precision": "fp64",
+                   "tol": args.tol},
+        "time_to_solution_s": round(elapsed / args.steps, 4),
+        "sweeps": stats[-1]["sweeps_max"],
+        "final_rel_increment": stats[-1]["final_err"],
+        "rho_est": stats[-1]["rho_est"],
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": None, "kernel": "sweep_f64_kernel",
+                     "avg_launch_ms": round(1e3 * kern_s / max(launches, 1), 4),
+                     "flops_per_launch": flops / max(launches, 1)},
+    }
+    if not args.no_cpu:
+        per_source = stats[-1]["gemm_flops"] / len(src)
+        rec["cpu_baseline"] = cpu_baseline(wl, per_source)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

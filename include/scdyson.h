@@ -1,0 +1,168 @@
+/*
+ * scdyson -- lattice strong-coupling Dyson solver for MI355X (gfx950).
+ *
+ * Computes the lowest-order lattice Green's function of the nonequilibrium
+ * strong-coupling expansion of Dirks, Mikelsons, Krishnamurthy and Freericks,
+ * arXiv:1309.5994: the trapped 2D Fermi-Hubbard model of eq. (model) on the
+ * discretised Kadanoff-Baym-Keldysh contour (Sec. IV.A, Fig. 1), with
+ *
+ *     G = S + S D G                                     (eq. Glatt, Sigma = 0)
+ *
+ * where S = blockdiag(S_i) holds each site's atomic-limit contour Green's
+ * function (Sec. III) and D is the nearest-neighbour hopping, diagonal in
+ * contour time with the quadrature weight of each contour point
+ * (eq. Ginvblockstruct).  The solve is the Dyson series of App. C summed by
+ * Jacobi sweeps X <- X0 + S D X over blocks of source-site columns
+ * (eq. blockedGMRESproblem), each sweep one fused hopping-stencil +
+ * batched complex contour GEMM on the MFMA units.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Contour: N_t = 2 n_real + n_imag points in contour order.
+ *   forward   a in [0, n_real):          t = t_min + a dt,              weight +dt
+ *   backward  a in [n_real, 2 n_real):   t = t_min + (2 n_real-1-a) dt, weight -dt
+ *   imaginary a = 2 n_real + m:          z = t_min - i (m+1) dtau,      weight -i dtau,
+ *             dtau = beta / n_imag.
+ *   The same-time partner (t + 0^+) of forward point a is 2 n_real - 1 - a.
+ * Lattice: Lx x Ly sites, site i = x * Ly + y, nearest neighbours
+ *   (x-1,y), (x+1,y), (x,y-1), (x,y+1) in that slot order; open edges drop the
+ *   bond, periodic lattices (periodic != 0) need Lx, Ly >= 3.
+ * Complex numbers are interleaved (re, im) doubles (C99 double complex).
+ * Inputs given per forward time (U, J) hold n_real values; the backward branch
+ * uses the value at the same physical time, the imaginary branch the value at
+ * t_min.
+ * Every pointer named "device" must be device memory of the current HIP
+ * device; "host" pointers are read before the call returns.  The caller owns
+ * all memory; the library allocates nothing and keeps no pointer after a call
+ * returns.  Arguments are validated before any work is enqueued.  Calls are
+ * re-entrant given distinct output and workspace buffers.  `stream` is a
+ * hipStream_t (NULL = the null stream).
+ */
+#ifndef SCDYSON_H
+#define SCDYSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define SCD_OK          0
+#define SCD_EINVAL     -1   /* bad argument: null pointer, size or range        */
+#define SCD_ENOMEM     -2   /* workspace smaller than scd_workspace_bytes()     */
+#define SCD_EHIP       -3   /* HIP runtime error; scd_last_error() has the text */
+#define SCD_ENOTCONV   -4   /* max_iter reached; outputs hold the last iterate  */
+#define SCD_EDIVERGED  -5   /* sweep increments grew for 8 sweeps in a row      */
+#define SCD_ENAN       -6   /* a NaN or Inf appeared in an iterate              */
+
+/* Sweep precision for dyson_iterate. */
+#define SCD_PREC_FP64   0   /* complex128 sweeps on FP64 MFMA                   */
+#define SCD_PREC_FP32   1   /* complex64 FP32-MFMA correction sweeps + FP64 refinement */
+
+typedef struct scd_problem {
+    int32_t Lx, Ly;      /* lattice extent                                      */
+    int32_t periodic;    /* 0 = open, 1 = periodic in both directions           */
+    int32_t n_real;      /* forward (= backward) real-time points, >= 1         */
+    int32_t n_imag;      /* imaginary-branch points, >= 1                       */
+    double  dt;          /* real-time step, > 0                                 */
+    double  beta;        /* inverse temperature of the initial state, > 0       */
+    double  mu;          /* chemical potential                                  */
+    double  t_min;       /* first real time, where the imaginary branch attaches */
+} scd_problem;
+
+typedef struct scd_stats {
+    int32_t status;         /* return code of the call                          */
+    int32_t n_blocks;       /* column blocks processed                          */
+    int32_t sweeps_total;   /* sweeps summed over blocks (all precisions)       */
+    int32_t sweeps_max;     /* largest sweep count of one block                 */
+    int32_t fp64_sweeps;    /* of which FP64 sweeps                             */
+    int32_t lowp_sweeps;    /* of which low-precision correction sweeps         */
+    double  final_err;      /* largest final relative increment (or residual) over blocks */
+    double  rho_est;        /* largest final contraction-ratio estimate e_n / e_{n-1}     */
+    double  gemm_flops;     /* algorithmic contour-GEMM flops: 8 N_t^3 per (target, source)
+                               pair inside the sweep's light cone (8 flops per complex MAC) */
+    double  seconds;        /* host wall time of the call                       */
+    double  sweep_kernel_seconds; /* summed HIP-event time of the sweep kernels  */
+    int32_t sweep_launches; /* sweep-kernel launches timed                      */
+    int32_t reserved;
+} scd_stats;
+
+/*
+ * Device workspace (bytes) that dyson_iterate needs for n_src source sites
+ * processed in column blocks of block_sites sources at precision prec.
+ * Returns SCD_OK and writes *bytes, or SCD_EINVAL.
+ */
+int scd_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites,
+                        int32_t prec, size_t* bytes);
+
+/*
+ * Atomic-limit contour Green's function of every site (Sec. III; the
+ * number-basis evaluation with the tabulated phases of eq. cumulanttabulation).
+ *   S_i[a][b] = -i [p0 e^{-i(th1_a - th1_b)} + p1 e^{-i(th2_a - th2_b)}]   a > b
+ *             = +i [p2 e^{-i(th1_a - th1_b)} + p3 e^{-i(th2_a - th2_b)}]   a <= b
+ * with eps_i = V_i - U(t_min)/2 - mu (eq. onsitelevels), p_nu the Boltzmann
+ * weights of the four number states at t_min (energies 0, eps, eps, 2 eps + U),
+ * th1 = int eps dz and th2 = int (eps + U(z)) dz along the contour from t_min
+ * (trapezoid rule for U on the forward grid).
+ *   V  device double[Lx*Ly]          trap potential per site
+ *   U  device double[n_real]         interaction per forward time
+ *   S  device complex128[N_r][N_t][N_t] output, row a contiguous
+ * Errors: SCD_EINVAL (bad sizes / nulls), SCD_EHIP.
+ */
+int sigma_build(const scd_problem* p, const double* V, const double* U, void* S,
+                void* stream);
+
+/*
+ * Solve G = S + S D G for the columns of the listed source sites.
+ *   S          device complex128[N_r][N_t][N_t] from sigma_build
+ *   J          device double[n_real]       hopping per forward time (all bonds)
+ *   src        host int32[n_src]           source sites, each in [0, N_r)
+ *   block_sites sources per column block (1..n_src); the block's iterate is
+ *              N_r x N_t x block_sites*N_t complex, sized for HBM by the caller
+ *   prec       SCD_PREC_FP64 or SCD_PREC_FP32
+ *   tol        stop when the relative max-norm increment of a sweep (FP64) or
+ *              the relative FP64 residual (FP32 + refinement) falls below tol,
+ *              with the contraction-corrected estimate e_n rho/(1-rho) also below tol
+ *   max_iter   sweep limit per block (FP64 sweeps for SCD_PREC_FP32)
+ *   G_cols     device complex128[N_r][N_t][n_src*N_t] or NULL: full columns,
+ *              column (s, b) = source src[s], contour time b
+ *   G_loc      device complex128[n_src][N_t][N_t]: G(src[s], src[s]) blocks
+ *   G_nn       device complex128[n_src][4][N_t][N_t]: G(nbr_d(src[s]), src[s]),
+ *              zero where the neighbour slot is empty
+ *   ws         device workspace of at least scd_workspace_bytes() bytes
+ *   st         host stats (may be NULL)
+ * Blocks the calling thread until every block has converged (one small
+ * device-to-host copy per sweep).  On SCD_ENOTCONV / SCD_EDIVERGED / SCD_ENAN
+ * the outputs of the failing block hold its last iterate and st is filled.
+ */
+int dyson_iterate(const scd_problem* p, const void* S, const double* J,
+                  const int32_t* src, int32_t n_src, int32_t block_sites,
+                  int32_t prec, double tol, int32_t max_iter,
+                  void* G_cols, void* G_loc, void* G_nn,
+                  void* ws, size_t ws_bytes, scd_stats* st, void* stream);
+
+/*
+ * Local observables of Sec. III.A from the blocks dyson_iterate returns.
+ *   n_s(t_a)     = Im G_loc[s][a][b(a)]                    (occupancy per spin)
+ *   ekin_s(t_a)  = Re( i sum_d J(t_a) G_nn[s][d][a][b(a)] ) (kinetic energy per spin)
+ * for forward points a in [0, n_real), b(a) = 2 n_real - 1 - a.
+ *   G_loc  device complex128[n_src][N_t][N_t]
+ *   G_nn   device complex128[n_src][4][N_t][N_t] (may be NULL if ekin_out is NULL)
+ *   J      device double[n_real]
+ *   n_out  device double[n_src][n_real]
+ *   ekin_out device double[n_src][n_real] or NULL
+ */
+int local_observables(const scd_problem* p, const void* G_loc, const void* G_nn,
+                      const double* J, int32_t n_src, double* n_out, double* ekin_out,
+                      void* stream);
+
+/* Message for the last failing call on this thread ("" if none). */
+const char* scd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCDYSON_H */

@@ -116,7 +116,9 @@ def dyson_columns_blocktri(S_blocks: np.ndarray, Lx: int, Ly: int,
         return r
 
     # Forward elimination: Dp_x = A_x - L_x Dp_{x-1}^-1 U_{x-1}, Rp_x likewise.
-    lus, uppers, rps = [], [], []
+    # The upper super-blocks are rebuilt during back substitution instead of
+    # being kept, which halves the memory of large lattices.
+    lus, rps = [], []
     prev_lu, prev_upper, prev_rp = None, None, None
     for x in range(Lx):
         diag, lower, upper = super_blocks(x)
@@ -124,16 +126,18 @@ def dyson_columns_blocktri(S_blocks: np.ndarray, Lx: int, Ly: int,
         if x > 0:
             diag = diag - lower @ sla.lu_solve(prev_lu, prev_upper)
             rp = rp - lower @ sla.lu_solve(prev_lu, prev_rp)
-        lu = sla.lu_factor(diag)
+        del lower
+        lu = sla.lu_factor(diag, overwrite_a=True)
         lus.append(lu)
-        uppers.append(upper)
         rps.append(rp)
         prev_lu, prev_upper, prev_rp = lu, upper, rp
+    del prev_upper
     # Back substitution.
     out = np.zeros((Lx, nb, n_rhs), dtype=np.complex128)
     out[Lx - 1] = sla.lu_solve(lus[Lx - 1], rps[Lx - 1])
     for x in range(Lx - 2, -1, -1):
-        out[x] = sla.lu_solve(lus[x], rps[x] - uppers[x] @ out[x + 1])
+        upper = super_blocks(x)[2]
+        out[x] = sla.lu_solve(lus[x], rps[x] - upper @ out[x + 1])
     return out.reshape(Lx * Ly, n_t, n_rhs)
 
 

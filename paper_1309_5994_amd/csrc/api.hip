@@ -1,0 +1,333 @@
+// C-ABI entry points of libscdyson: argument validation, workspace layout,
+// column-block scheduling and the host side of the convergence loop.
+#include <algorithm>
+#include <chrono>
+#include <cstdlib>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace scd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+    return fail(SCD_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define SCD_HIP(call, where)                         \
+    do {                                             \
+        hipError_t e_ = (call);                      \
+        if (e_ != hipSuccess) return hip_fail(e_, where); \
+    } while (0)
+
+int check_problem(const scd_problem* p, int max_nt, Geom* g) {
+    if (!p) return fail(SCD_EINVAL, "problem is NULL");
+    if (p->Lx < 1 || p->Ly < 1) return fail(SCD_EINVAL, "lattice extent must be >= 1");
+    if ((int64_t)p->Lx * p->Ly > 65535) return fail(SCD_EINVAL, "at most 65535 sites");
+    if (p->periodic != 0 && p->periodic != 1) return fail(SCD_EINVAL, "periodic must be 0 or 1");
+    if (p->periodic && (p->Lx < 3 || p->Ly < 3))
+        return fail(SCD_EINVAL, "periodic lattices need Lx, Ly >= 3");
+    if (p->n_real < 1 || p->n_imag < 1) return fail(SCD_EINVAL, "n_real and n_imag must be >= 1");
+    const int64_t n_t = 2 * (int64_t)p->n_real + p->n_imag;
+    if (n_t > max_nt) return fail(SCD_EINVAL, "contour has %lld points, at most %d supported",
+                                  (long long)n_t, max_nt);
+    if (!(p->dt > 0.0) || !std::isfinite(p->dt)) return fail(SCD_EINVAL, "dt must be > 0");
+    if (!(p->beta > 0.0) || !std::isfinite(p->beta)) return fail(SCD_EINVAL, "beta must be > 0");
+    if (!std::isfinite(p->mu) || !std::isfinite(p->t_min))
+        return fail(SCD_EINVAL, "mu and t_min must be finite");
+    g->Lx = p->Lx;
+    g->Ly = p->Ly;
+    g->periodic = p->periodic;
+    g->n_r = p->Lx * p->Ly;
+    g->n_real = p->n_real;
+    g->n_imag = p->n_imag;
+    g->n_t = (int)n_t;
+    g->mt = (g->n_t + kTile - 1) / kTile;
+    g->mp = g->mt * kTile;
+    g->dt = p->dt;
+    g->beta = p->beta;
+    g->mu = p->mu;
+    g->t_min = p->t_min;
+    g->dtau = p->beta / p->n_imag;
+    return SCD_OK;
+}
+
+struct Layout {
+    int ldx, ntn, nwg;
+    size_t off_st, off_x0, off_x1, off_partial, off_slot, off_src, total;
+};
+
+Layout layout(const Geom& g, int n_src, int block_sites) {
+    Layout L;
+    const int bs = block_sites < n_src ? block_sites : n_src;
+    L.ldx = ((bs * g.n_t + kColsPerWG - 1) / kColsPerWG) * kColsPerWG;
+    L.ntn = L.ldx / kColsPerWG;
+    L.nwg = g.n_r * L.ntn;
+    size_t off = 0;
+    L.off_st = off;
+    off += align256((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
+    L.off_x0 = off;
+    off += align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
+    L.off_x1 = off;
+    off += align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
+    L.off_partial = off;
+    off += align256((size_t)L.nwg * 3 * sizeof(double));
+    L.off_slot = off;
+    off += align256(4 * sizeof(unsigned long long));
+    L.off_src = off;
+    off += align256((size_t)n_src * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+// Two timing events, destroyed on every exit path.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t create() {
+        hipError_t e = hipEventCreate(&a);
+        if (e == hipSuccess) e = hipEventCreate(&b);
+        return e;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+double bits_to_double(unsigned long long u) {
+    double d;
+    std::memcpy(&d, &u, sizeof d);
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* scd_last_error(void) { return g_last_error.c_str(); }
+
+int scd_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites, int32_t prec,
+                        size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
+    if (n_src < 1 || n_src > g.n_r) return fail(SCD_EINVAL, "n_src must be in [1, N_r]");
+    if (block_sites < 1) return fail(SCD_EINVAL, "block_sites must be >= 1");
+    if (prec != SCD_PREC_FP64) return fail(SCD_EINVAL, "unsupported precision %d", prec);
+    *bytes = layout(g, n_src, block_sites).total;
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int sigma_build(const scd_problem* p, const double* V, const double* U, void* S, void* stream) {
+    Geom g;
+    int rc = check_problem(p, 1024, &g);
+    if (rc) return rc;
+    if (g.n_real > 512) return fail(SCD_EINVAL, "at most 512 real-time points");
+    if (!V || !U || !S) return fail(SCD_EINVAL, "V, U and S must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    SCD_HIP(launch_sigma_build(g, V, U, (double2*)S, st), "sigma_build launch");
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int local_observables(const scd_problem* p, const void* G_loc, const void* G_nn, const double* J,
+                      int32_t n_src, double* n_out, double* ekin_out, void* stream) {
+    Geom g;
+    int rc = check_problem(p, 1 << 20, &g);
+    if (rc) return rc;
+    if (n_src < 1) return fail(SCD_EINVAL, "n_src must be >= 1");
+    if (!G_loc || !n_out) return fail(SCD_EINVAL, "G_loc and n_out must be non-NULL");
+    if (ekin_out && (!G_nn || !J)) return fail(SCD_EINVAL, "ekin_out needs G_nn and J");
+    hipStream_t st = (hipStream_t)stream;
+    SCD_HIP(launch_observables(g, (const double2*)G_loc, (const double2*)G_nn, J, n_src, n_out,
+                               ekin_out, st),
+            "local_observables launch");
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int dyson_iterate(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                  int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
+                  void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
+                  scd_stats* st_out, void* stream) {
+    const auto t_start = std::chrono::steady_clock::now();
+    scd_stats stats;
+    std::memset(&stats, 0, sizeof stats);
+    auto finish = [&](int code) {
+        stats.status = code;
+        stats.seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (st_out) *st_out = stats;
+        return code;
+    };
+
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return finish(rc);
+    if (!S || !J || !src || !G_loc || !ws)
+        return finish(fail(SCD_EINVAL, "S, J, src, G_loc and ws must be non-NULL"));
+    if (n_src < 1 || n_src > g.n_r) return finish(fail(SCD_EINVAL, "n_src must be in [1, N_r]"));
+    if (block_sites < 1) return finish(fail(SCD_EINVAL, "block_sites must be >= 1"));
+    if (prec != SCD_PREC_FP64) return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
+    if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
+    for (int s = 0; s < n_src; ++s)
+        if (src[s] < 0 || src[s] >= g.n_r)
+            return finish(fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r));
+    const Layout L = layout(g, n_src, block_sites);
+    if (ws_bytes < L.total)
+        return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total));
+
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    double2* St = (double2*)(base + L.off_st);
+    double2* Xa = (double2*)(base + L.off_x0);
+    double2* Xb = (double2*)(base + L.off_x1);
+    double* partial = (double*)(base + L.off_partial);
+    unsigned long long* slot = (unsigned long long*)(base + L.off_slot);
+    int* src_dev = (int*)(base + L.off_src);
+
+    SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
+            "copy src");
+    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, St, st), "scale_transpose launch");
+    SCD_HIP(hipStreamSynchronize(st), "setup sync");
+    EventPair evs;
+    SCD_HIP(evs.create(), "event create");
+    hipEvent_t ev0 = evs.a, ev1 = evs.b;
+
+    const int bs_max = block_sites < n_src ? block_sites : n_src;
+    double worst_err = 0.0, worst_rho = 0.0;
+    int final_code = SCD_OK;
+    for (int blk_start = 0; blk_start < n_src; blk_start += bs_max) {
+        const int bs = (n_src - blk_start) < bs_max ? (n_src - blk_start) : bs_max;
+        const int* src_blk = src_dev + blk_start;
+        SweepArgs a;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.periodic = g.periodic;
+        a.n_r = g.n_r;
+        a.n_t = g.n_t;
+        a.ldx = L.ldx;
+        a.ntn = L.ntn;
+        a.bs = bs;
+        a.lc_sweep = 0;
+        // Pairs (target, source) by lattice distance: sweep n reaches distance n.
+        std::vector<double> within(g.Lx + g.Ly + 1, 0.0);
+        for (int s = 0; s < bs; ++s) {
+            const int j = src[blk_start + s];
+            const int xj = j / g.Ly, yj = j % g.Ly;
+            for (int i = 0; i < g.n_r; ++i) {
+                int dx = std::abs(i / g.Ly - xj), dy = std::abs(i % g.Ly - yj);
+                if (g.periodic) {
+                    dx = std::min(dx, g.Lx - dx);
+                    dy = std::min(dy, g.Ly - dy);
+                }
+                within[dx + dy] += 1.0;
+            }
+        }
+        for (size_t d = 1; d < within.size(); ++d) within[d] += within[d - 1];
+        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, Xa, Xb, st),
+                "init_block launch");
+        double2* cur = Xa;
+        double2* nxt = Xb;
+        double e_prev = 0.0, rho = 0.0, e_n = 0.0, d_prev = 0.0;
+        int grow = 0, n = 0, code = SCD_ENOTCONV;
+        for (n = 1; n <= max_iter; ++n) {
+            a.lc_sweep = n - 1;
+            SCD_HIP(hipEventRecord(ev0, st), "event record");
+            SCD_HIP(launch_sweep_f64(g, a, St, (const double2*)S, src_blk, cur, nxt, partial, st),
+                    "sweep launch");
+            SCD_HIP(hipEventRecord(ev1, st), "event record");
+            SCD_HIP(hipMemsetAsync(slot, 0, 4 * sizeof(unsigned long long), st), "slot clear");
+            SCD_HIP(launch_reduce_max3(partial, L.nwg, slot, st), "reduce launch");
+            unsigned long long h[3];
+            SCD_HIP(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st), "slot copy");
+            SCD_HIP(hipStreamSynchronize(st), "sweep sync");
+            double2* tmp = cur;
+            cur = nxt;
+            nxt = tmp;
+            stats.fp64_sweeps++;
+            {
+                const size_t dmax_idx = within.size() - 1;
+                const double pairs = within[(size_t)n < dmax_idx ? (size_t)n : dmax_idx];
+                stats.gemm_flops += 8.0 * g.n_t * (double)g.n_t * (double)g.n_t * pairs;
+                float ms = 0.0f;
+                SCD_HIP(hipEventElapsedTime(&ms, ev0, ev1), "event time");
+                stats.sweep_kernel_seconds += 1e-3 * ms;
+                stats.sweep_launches++;
+            }
+            const double dmax = bits_to_double(h[0]);
+            const double xmax = bits_to_double(h[1]);
+            if (bits_to_double(h[2]) != 0.0 || !std::isfinite(dmax) || !std::isfinite(xmax)) {
+                code = fail(SCD_ENAN, "NaN or Inf in the iterate of block at source %d, sweep %d",
+                            blk_start, n);
+                break;
+            }
+            e_n = xmax > 0.0 ? dmax / xmax : 0.0;
+            if (n >= 2 && e_prev > 0.0) rho = e_n / e_prev;
+            if (e_n == 0.0) {
+                code = SCD_OK;
+                break;
+            }
+            if (e_n <= tol && n >= 2 &&
+                (e_n <= 1e-2 * tol || (rho < 1.0 && e_n * rho / (1.0 - rho) <= tol))) {
+                code = SCD_OK;
+                break;
+            }
+            // A convergent Dyson series has shrinking increments; a divergent one
+            // grows them geometrically (the relative increment stays O(1)).
+            grow = (n >= 2 && dmax > d_prev) ? grow + 1 : 0;
+            if (grow >= 8) {
+                code = fail(SCD_EDIVERGED,
+                            "sweep increments grew 8 times in a row (|dX|=%g, sweep %d)", dmax, n);
+                break;
+            }
+            e_prev = e_n;
+            d_prev = dmax;
+        }
+        if (n > max_iter) n = max_iter;
+        if (code == SCD_ENOTCONV)
+            fail(SCD_ENOTCONV, "block at source %d not converged after %d sweeps (e=%g)", blk_start,
+                 max_iter, e_n);
+        stats.n_blocks++;
+        stats.sweeps_total += n;
+        if (n > stats.sweeps_max) stats.sweeps_max = n;
+        worst_err = e_n > worst_err ? e_n : worst_err;
+        worst_rho = rho > worst_rho ? rho : worst_rho;
+        SCD_HIP(launch_extract(g, cur, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
+                               (double2*)G_loc, (double2*)G_nn, st),
+                "extract launch");
+        if (code != SCD_OK) {
+            final_code = code;
+            break;
+        }
+    }
+    SCD_HIP(hipStreamSynchronize(st), "final sync");
+    stats.final_err = worst_err;
+    stats.rho_est = worst_rho;
+    if (final_code == SCD_OK) g_last_error.clear();
+    return finish(final_code);
+}
+
+}  // extern "C"

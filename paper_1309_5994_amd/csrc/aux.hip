@@ -1,0 +1,195 @@
+// Memory-bound helper kernels of the Dyson solve: operand preparation, block
+// initialisation, the convergence reduction, extraction of the kept blocks and
+// the local observables (Sec. III.A of arXiv:1309.5994).
+#include "internal.h"
+
+namespace scd {
+namespace {
+
+// St[i][c][a] = S_i[a][c] * w_c J(z_c) with zero padding to mp x mp.
+// The contour weight and hopping of the summed-over time c are folded into the
+// GEMM's left operand once, so a sweep is X' = X0 + St^T (sum of neighbour
+// tiles).  32x32 tiles transposed through LDS keep both sides coalesced.
+__global__ __launch_bounds__(256)
+void scale_transpose_kernel(const double2* __restrict__ S, const double* __restrict__ J,
+                            double2* __restrict__ St, Geom g) {
+    __shared__ double2 tile[32][33];
+    const int site = blockIdx.z;
+    const int a0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+    const double2* Si = S + (size_t)site * g.n_t * g.n_t;
+    for (int r = ty; r < 32; r += 8) {
+        const int a = a0 + r, c = c0 + tx;
+        double2 v = make_double2(0.0, 0.0);
+        if (a < g.n_t && c < g.n_t) {
+            const double2 s = Si[(size_t)a * g.n_t + c];
+            const double2 w = contour_wj(c, g.n_real, g.dt, g.dtau, J);
+            v = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    double2* Sti = St + (size_t)site * g.mp * g.mp;
+    for (int r = ty; r < 32; r += 8) {
+        const int c = c0 + r, a = a0 + tx;
+        if (c < g.mp && a < g.mp) Sti[(size_t)c * g.mp + a] = tile[tx][r];
+    }
+}
+
+// X = X0 = E_J S (the preconditioned unit-vector bundle of the block): zero
+// except the (j, j) sub-blocks, which hold S_j.  Xn is cleared.
+__global__ __launch_bounds__(256)
+void init_block_kernel(const double2* __restrict__ S, const int* __restrict__ src_blk, int bs,
+                       int ldx, double2* __restrict__ X, double2* __restrict__ Xn, Geom g) {
+    const size_t total = (size_t)g.n_r * g.mp * ldx;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int col = (int)(e % ldx);
+        const size_t r = e / ldx;
+        const int a = (int)(r % g.mp);
+        const int i = (int)(r / g.mp);
+        double2 v = make_double2(0.0, 0.0);
+        const int s = col / g.n_t;
+        if (s < bs && a < g.n_t && src_blk[s] == i) {
+            const int b = col - s * g.n_t;
+            v = S[((size_t)i * g.n_t + a) * g.n_t + b];
+        }
+        X[e] = v;
+        Xn[e] = make_double2(0.0, 0.0);
+    }
+}
+
+// Order-independent max of the per-workgroup (|dX|max, |X|max, nan flag)
+// partials into one slot; values are non-negative so their bit patterns order
+// like unsigned integers.
+__global__ __launch_bounds__(256)
+void reduce_max3_kernel(const double* __restrict__ partial, int n,
+                        unsigned long long* __restrict__ slot) {
+    __shared__ double red[3][256];
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        m0 = fmax(m0, partial[3 * k + 0]);
+        m1 = fmax(m1, partial[3 * k + 1]);
+        m2 = fmax(m2, partial[3 * k + 2]);
+    }
+    red[0][threadIdx.x] = m0;
+    red[1][threadIdx.x] = m1;
+    red[2][threadIdx.x] = m2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            for (int q = 0; q < 3; ++q)
+                red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 3; ++q)
+            atomicMax(slot + q, (unsigned long long)__double_as_longlong(red[q][0]));
+    }
+}
+
+// Copy the kept blocks of a converged column block out of the iterate.
+__global__ __launch_bounds__(256)
+void extract_kernel(const double2* __restrict__ X, int ldx, const int* __restrict__ src_blk,
+                    int bs, int blk_start, int n_src, double2* __restrict__ G_cols,
+                    double2* __restrict__ G_loc, double2* __restrict__ G_nn, Geom g) {
+    const int n_t = g.n_t;
+    const size_t blk_elems = (size_t)bs * n_t * n_t;
+    // Part 1: local and neighbour blocks, (s, slot 0..4, a, b).
+    const size_t kept = blk_elems * 5;
+    const size_t cols_total = G_cols ? (size_t)g.n_r * n_t * bs * n_t : 0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < kept + cols_total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        if (e < kept) {
+            const int b = (int)(e % n_t);
+            const int a = (int)((e / n_t) % n_t);
+            const int q = (int)((e / ((size_t)n_t * n_t)) % 5);
+            const int s = (int)(e / ((size_t)n_t * n_t * 5));
+            const int j = src_blk[s];
+            int k = j;
+            if (q > 0) {
+                int nb[4];
+                site_neighbours(j, g.Lx, g.Ly, g.periodic, nb);
+                k = nb[q - 1];
+            }
+            double2 v = make_double2(0.0, 0.0);
+            if (k >= 0) v = X[((size_t)k * g.mp + a) * ldx + (size_t)s * n_t + b];
+            const size_t gs = (size_t)(blk_start + s);
+            if (q == 0) {
+                G_loc[(gs * n_t + a) * n_t + b] = v;
+            } else if (G_nn) {
+                G_nn[((gs * 4 + (q - 1)) * n_t + a) * n_t + b] = v;
+            }
+        } else {
+            const size_t f = e - kept;
+            const int col = (int)(f % ((size_t)bs * n_t));
+            const int a = (int)((f / ((size_t)bs * n_t)) % n_t);
+            const int k = (int)(f / ((size_t)bs * n_t * n_t));
+            G_cols[((size_t)k * n_t + a) * ((size_t)n_src * n_t) + (size_t)blk_start * n_t + col] =
+                X[((size_t)k * g.mp + a) * ldx + col];
+        }
+    }
+}
+
+// n_s(t_a) = Im G_loc[s][a][b(a)], ekin_s(t_a) = Re(i J(t_a) sum_d G_nn[s][d][a][b(a)]).
+__global__ __launch_bounds__(256)
+void observables_kernel(const double2* __restrict__ G_loc, const double2* __restrict__ G_nn,
+                        const double* __restrict__ J, int n_src, double* __restrict__ n_out,
+                        double* __restrict__ ekin_out, Geom g) {
+    const int n_t = g.n_t, n_real = g.n_real;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_src * n_real) return;
+    const int s = e / n_real, a = e - (e / n_real) * n_real;
+    const int b = 2 * n_real - 1 - a;
+    n_out[e] = G_loc[((size_t)s * n_t + a) * n_t + b].y;
+    if (ekin_out) {
+        double im = 0.0;
+        for (int d = 0; d < 4; ++d) im += G_nn[(((size_t)s * 4 + d) * n_t + a) * n_t + b].y;
+        // Re(i J (x + i y)) = -J y
+        ekin_out[e] = -J[a] * im;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
+                                  hipStream_t st) {
+    dim3 grid((g.mp + 31) / 32, (g.mp + 31) / 32, g.n_r);
+    hipLaunchKernelGGL(scale_transpose_kernel, grid, dim3(256), 0, st, S, J, St, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_block(const Geom& g, const double2* S, const int* src_blk, int bs, int ldx,
+                             double2* X, double2* Xn, hipStream_t st) {
+    hipLaunchKernelGGL(init_block_kernel, dim3(4096), dim3(256), 0, st, S, src_blk, bs, ldx, X, Xn, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_max3(const double* partial, int n, unsigned long long* slot,
+                              hipStream_t st) {
+    int blocks = (n + 255) / 256;
+    if (blocks > 256) blocks = 256;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(reduce_max3_kernel, dim3(blocks), dim3(256), 0, st, partial, n, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* src_blk, int bs,
+                          int blk_start, int n_src, double2* G_cols, double2* G_loc, double2* G_nn,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(extract_kernel, dim3(4096), dim3(256), 0, st, X, ldx, src_blk, bs,
+                       blk_start, n_src, G_cols, G_loc, G_nn, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const Geom& g, const double2* G_loc, const double2* G_nn,
+                              const double* J, int n_src, double* n_out, double* ekin_out,
+                              hipStream_t st) {
+    const int total = n_src * g.n_real;
+    hipLaunchKernelGGL(observables_kernel, dim3((total + 255) / 256), dim3(256), 0, st, G_loc,
+                       G_nn, J, n_src, n_out, ekin_out, g);
+    return hipGetLastError();
+}
+
+}  // namespace scd

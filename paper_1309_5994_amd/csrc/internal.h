@@ -1,0 +1,96 @@
+// Internal declarations shared by the scdyson translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/scdyson.h"
+
+namespace scd {
+
+// Largest contour length the sweep kernels are instantiated for (row tiles of
+// 16 contour points, 1..kMaxRowTiles).
+constexpr int kTile = 16;
+constexpr int kMaxRowTiles = 16;
+constexpr int kMaxNt = kTile * kMaxRowTiles;     // 256
+constexpr int kColsPerWG = 64;                   // column tile of one sweep workgroup
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// Geometry of one problem, derived on the host from scd_problem.
+struct Geom {
+    int Lx, Ly, periodic;
+    int n_r;        // sites
+    int n_real, n_imag;
+    int n_t;        // contour points
+    int mt;         // row tiles: n_t padded to mp = 16 * mt
+    int mp;
+    double dt, beta, mu, t_min, dtau;
+};
+
+// Parameters of one sweep launch (one column block).
+struct SweepArgs {
+    int Lx, Ly, periodic;
+    int n_r, n_t;
+    int ldx;        // padded column count of the block iterate (multiple of 64)
+    int ntn;        // column tiles per site = ldx / 64
+    int bs;         // source sites in this block
+    int lc_sweep;   // sweeps already applied (light cone radius) or -1 to disable skipping
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Site neighbours in slot order (x-1,y), (x+1,y), (x,y-1), (x,y+1); -1 if absent.
+__host__ __device__ inline void site_neighbours(int i, int Lx, int Ly, int periodic, int nb[4]) {
+    const int x = i / Ly, y = i - (i / Ly) * Ly;
+    int xs[4] = {x - 1, x + 1, x, x};
+    int ys[4] = {y, y, y - 1, y + 1};
+    for (int d = 0; d < 4; ++d) {
+        int xx = xs[d], yy = ys[d];
+        if (periodic) {
+            xx = (xx + Lx) % Lx;
+            yy = (yy + Ly) % Ly;
+            nb[d] = xx * Ly + yy;
+        } else {
+            nb[d] = (xx >= 0 && xx < Lx && yy >= 0 && yy < Ly) ? xx * Ly + yy : -1;
+        }
+    }
+}
+
+// Hopping weight w(z_c) * J(z_c) of contour point c, as (re, im).
+__device__ inline double2 contour_wj(int c, int n_real, double dt, double dtau, const double* J) {
+    if (c < n_real) return make_double2(dt * J[c], 0.0);
+    if (c < 2 * n_real) return make_double2(-dt * J[2 * n_real - 1 - c], 0.0);
+    return make_double2(0.0, -dtau * J[0]);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical tiles so tiles sharing operands share an L2.
+__device__ inline int xcd_remap(int bid, int nb) {
+    const int per = nb >> 3;
+    if (bid >= (per << 3)) return bid;
+    return (bid & 7) * per + (bid >> 3);
+}
+
+// ---- launchers (each returns hipError_t of the launch) ----
+hipError_t launch_sigma_build(const Geom& g, const double* V, const double* U, double2* S,
+                              hipStream_t st);
+hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
+                                  hipStream_t st);
+hipError_t launch_init_block(const Geom& g, const double2* S, const int* src_blk, int bs, int ldx,
+                             double2* X, double2* Xn, hipStream_t st);
+hipError_t launch_sweep_f64(const Geom& g, const SweepArgs& a, const double2* St, const double2* S,
+                            const int* src_blk, const double2* X, double2* Xn, double* partial,
+                            hipStream_t st);
+hipError_t launch_reduce_max3(const double* partial, int n, unsigned long long* slot,
+                              hipStream_t st);
+hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* src_blk, int bs,
+                          int blk_start, int n_src, double2* G_cols, double2* G_loc, double2* G_nn,
+                          hipStream_t st);
+hipError_t launch_observables(const Geom& g, const double2* G_loc, const double2* G_nn,
+                              const double* J, int n_src, double* n_out, double* ekin_out,
+                              hipStream_t st);
+
+}  // namespace scd

@@ -1,0 +1,210 @@
+"""ctypes binding of libscdyson.so: argument marshalling only.
+
+Every entry point of ``include/scdyson.h`` is exposed under the same name.
+Tensors are PyTorch tensors on the current HIP device (complex128 for Green's
+functions, float64 for real inputs); the current torch stream is passed to the
+library.  No arithmetic of the method happens here, and there is no fallback:
+if the library is missing the first call raises.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libscdyson.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "scdyson.h")
+
+SCD_OK, SCD_EINVAL, SCD_ENOMEM, SCD_EHIP, SCD_ENOTCONV, SCD_EDIVERGED, SCD_ENAN = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32 = 0, 1
+ERROR_NAMES = {0: "SCD_OK", -1: "SCD_EINVAL", -2: "SCD_ENOMEM", -3: "SCD_EHIP",
+               -4: "SCD_ENOTCONV", -5: "SCD_EDIVERGED", -6: "SCD_ENAN"}
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_int32), ("Ly", ctypes.c_int32), ("periodic", ctypes.c_int32),
+                ("n_real", ctypes.c_int32), ("n_imag", ctypes.c_int32),
+                ("dt", ctypes.c_double), ("beta", ctypes.c_double), ("mu", ctypes.c_double),
+                ("t_min", ctypes.c_double)]
+
+    @property
+    def n_r(self):
+        return self.Lx * self.Ly
+
+    @property
+    def n_t(self):
+        return 2 * self.n_real + self.n_imag
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_blocks", ctypes.c_int32),
+                ("sweeps_total", ctypes.c_int32), ("sweeps_max", ctypes.c_int32),
+                ("fp64_sweeps", ctypes.c_int32), ("lowp_sweeps", ctypes.c_int32),
+                ("final_err", ctypes.c_double), ("rho_est", ctypes.c_double),
+                ("gemm_flops", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("sweep_kernel_seconds", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ScdError(RuntimeError):
+    def __init__(self, code, message, stats=None):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {message}")
+        self.code = code
+        self.stats = stats
+
+
+_lib = None
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+
+
+def lib():
+    """Load libscdyson.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing; build it with "
+                           "`python -m paper_1309_5994_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    L.scd_last_error.restype = ctypes.c_char_p
+    L.scd_last_error.argtypes = []
+    L.scd_workspace_bytes.restype = ctypes.c_int
+    L.scd_workspace_bytes.argtypes = [_P(Problem), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      _P(ctypes.c_size_t)]
+    L.sigma_build.restype = ctypes.c_int
+    L.sigma_build.argtypes = [_P(Problem), _vp, _vp, _vp, _vp]
+    L.dyson_iterate.restype = ctypes.c_int
+    L.dyson_iterate.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.local_observables.restype = ctypes.c_int
+    L.local_observables.argtypes = [_P(Problem), _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions that include/scdyson.h declares."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def last_error() -> str:
+    return lib().scd_last_error().decode()
+
+
+def _check(rc, stats=None):
+    if rc != SCD_OK:
+        raise ScdError(rc, last_error(), stats)
+
+
+def problem(Lx, Ly, n_real, n_imag, dt, beta, mu=0.0, t_min=0.0, periodic=False) -> Problem:
+    return Problem(int(Lx), int(Ly), int(bool(periodic)), int(n_real), int(n_imag), float(dt),
+                   float(beta), float(mu), float(t_min))
+
+
+def problem_from_workload(wl) -> Problem:
+    return problem(wl.Lx, wl.Ly, wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.mu, wl.t_min,
+                   wl.periodic)
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _need(t, dtype, shape, name):
+    import torch
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def workspace_bytes(prob: Problem, n_src, block_sites, prec=PREC_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_workspace_bytes(ctypes.byref(prob), int(n_src), int(block_sites), int(prec),
+                                     ctypes.byref(out)))
+    return out.value
+
+
+def sigma_build(prob: Problem, V, U, S=None, stream=None):
+    """S[N_r, N_t, N_t] (complex128) from V[N_r], U[n_real] (float64, on device)."""
+    import torch
+    _need(V, torch.float64, (prob.n_r,), "V")
+    _need(U, torch.float64, (prob.n_real,), "U")
+    if S is None:
+        S = torch.empty((prob.n_r, prob.n_t, prob.n_t), dtype=torch.complex128, device=V.device)
+    _need(S, torch.complex128, (prob.n_r, prob.n_t, prob.n_t), "S")
+    _check(lib().sigma_build(ctypes.byref(prob), _ptr(V), _ptr(U), _ptr(S), _stream(stream)))
+    return S
+
+
+def dyson_iterate(prob: Problem, S, J, src, block_sites=None, prec=PREC_FP64, tol=1e-12,
+                  max_iter=500, want_cols=False, want_nn=True, ws=None, out=None, stream=None):
+    """Columns of G for the source sites ``src``.
+
+    Returns dict(G_loc [n_src,N_t,N_t], G_nn [n_src,4,N_t,N_t] or None,
+    G_cols [N_r,N_t,n_src*N_t] or None, stats dict).  Raises ScdError on
+    failure (the error carries the stats).
+    """
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+    n_src = int(src.size)
+    block_sites = n_src if block_sites is None else int(block_sites)
+    _need(S, torch.complex128, (n_r, n_t, n_t), "S")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    dev = S.device
+    out = dict(out or {})
+    G_loc = out.get("G_loc")
+    if G_loc is None:
+        G_loc = torch.empty((n_src, n_t, n_t), dtype=torch.complex128, device=dev)
+    G_nn = out.get("G_nn")
+    if want_nn and G_nn is None:
+        G_nn = torch.empty((n_src, 4, n_t, n_t), dtype=torch.complex128, device=dev)
+    G_cols = out.get("G_cols")
+    if want_cols and G_cols is None:
+        G_cols = torch.empty((n_r, n_t, n_src * n_t), dtype=torch.complex128, device=dev)
+    need = workspace_bytes(prob, n_src, block_sites, prec)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st = Stats()
+    rc = lib().dyson_iterate(ctypes.byref(prob), _ptr(S), _ptr(J),
+                             src.ctypes.data_as(_P(ctypes.c_int32)), n_src, block_sites, int(prec),
+                             float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc), _ptr(G_nn),
+                             _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
+                             _stream(stream))
+    _check(rc, st.as_dict())
+    return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
+
+
+def local_observables(prob: Problem, G_loc, G_nn, J, want_ekin=True, stream=None):
+    """(n [n_src, n_real], ekin [n_src, n_real] or None) on the device."""
+    import torch
+    n_src = int(G_loc.shape[0])
+    _need(G_loc, torch.complex128, (n_src, prob.n_t, prob.n_t), "G_loc")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    n = torch.empty((n_src, prob.n_real), dtype=torch.float64, device=G_loc.device)
+    ekin = None
+    if want_ekin:
+        _need(G_nn, torch.complex128, (n_src, 4, prob.n_t, prob.n_t), "G_nn")
+        ekin = torch.empty_like(n)
+    _check(lib().local_observables(ctypes.byref(prob), _ptr(G_loc), _ptr(G_nn if want_ekin else None),
+                                   _ptr(J), n_src, _ptr(n), _ptr(ekin), _stream(stream)))
+    return n, ekin

@@ -1,0 +1,77 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, it exports
+every function include/scdyson.h declares, and argument validation rejects bad
+input before any HIP call (so these run on a machine without a GPU)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1309_5994_amd import scdyson as B
+
+
+def test_library_exports_every_declared_function():
+    L = B.lib()
+    names = B.header_functions()
+    assert {"sigma_build", "dyson_iterate", "local_observables", "scd_workspace_bytes",
+            "scd_last_error"} <= set(names)
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_layout():
+    p = B.problem(4, 4, 20, 10, 0.1, 5.0)
+    n = B.workspace_bytes(p, 16, 16)
+    # S operand (64x64 padded) + two 16 x 64 x 832 iterates, complex128
+    assert n >= 16 * 64 * 64 * 16 + 2 * 16 * 64 * 832 * 16
+    assert B.workspace_bytes(p, 16, 4) < n
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(Lx=0), "lattice extent"),
+    (dict(periodic=1, Lx=2), "periodic"),
+    (dict(n_real=0), "n_real"),
+    (dict(n_real=200), "contour"),
+    (dict(dt=0.0), "dt"),
+    (dict(beta=-1.0), "beta"),
+])
+def test_problem_validation(kw, msg):
+    base = dict(Lx=4, Ly=4, periodic=0, n_real=20, n_imag=10, dt=0.1, beta=5.0, mu=0.0, t_min=0.0)
+    base.update(kw)
+    p = B.Problem(**base)
+    out = ctypes.c_size_t(0)
+    rc = B.lib().scd_workspace_bytes(ctypes.byref(p), 1, 1, 0, ctypes.byref(out))
+    assert rc == B.SCD_EINVAL
+    assert msg in B.last_error()
+
+
+def test_dyson_iterate_rejects_bad_arguments_before_launch():
+    L = B.lib()
+    p = B.problem(3, 3, 5, 4, 0.1, 2.0)
+    src = np.array([0, 9], dtype=np.int32)          # 9 is outside the 3x3 lattice
+    fake = ctypes.c_void_p(0x1000)                   # never dereferenced: validation fails first
+    st = B.Stats()
+    rc = L.dyson_iterate(ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         2, 2, 0, 1e-12, 10, None, fake, None, fake, ctypes.c_size_t(1 << 40),
+                         ctypes.byref(st), None)
+    assert rc == B.SCD_EINVAL and "src[1]" in B.last_error()
+    assert st.status == B.SCD_EINVAL
+    rc = L.dyson_iterate(ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         1, 1, 0, 1e-12, 10, None, fake, None, fake, ctypes.c_size_t(16),
+                         ctypes.byref(st), None)
+    assert rc == B.SCD_ENOMEM
+    rc = L.dyson_iterate(ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         1, 1, 7, 1e-12, 10, None, fake, None, fake, ctypes.c_size_t(1 << 40),
+                         ctypes.byref(st), None)
+    assert rc == B.SCD_EINVAL and "precision" in B.last_error()
+    rc = L.dyson_iterate(ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         1, 1, 0, 0.0, 10, None, fake, None, fake, ctypes.c_size_t(1 << 40),
+                         ctypes.byref(st), None)
+    assert rc == B.SCD_EINVAL and "tol" in B.last_error()
+
+
+def test_sigma_build_and_observables_reject_nulls():
+    L = B.lib()
+    p = B.problem(2, 2, 3, 2, 0.1, 1.0)
+    assert L.sigma_build(ctypes.byref(p), None, None, None, None) == B.SCD_EINVAL
+    assert L.local_observables(ctypes.byref(p), None, None, None, 1, None, None, None) == B.SCD_EINVAL
+    assert L.sigma_build(None, None, None, None, None) == B.SCD_EINVAL

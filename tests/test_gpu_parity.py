@@ -1,0 +1,153 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU FP64 oracle on
+the same seeded inputs.  Bars: sigma_build elementwise to 1e-13 relative to
+max|S|; the FP64 Dyson path to 1e-12 relative max-norm on G; densities and
+kinetic energies to 1e-12 absolute."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_5994_amd import workloads as W
+from helpers import oracle_setup, oracle_dense, dense_columns, rel_maxnorm, gpu_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _B():
+    from paper_1309_5994_amd import scdyson as B
+    return B
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("wl", [W.config(1), W.custom(3, 5, 7, 5, seed=4),
+                                W.custom(2, 3, 150, 40, beta=3.0, seed=8)],
+                         ids=["cfg1", "ragged3x5", "long_contour"])
+def test_sigma_build_matches_oracle(wl, device):
+    B = _B()
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = _np(B.sigma_build(prob, V, U))
+    _, S_ref = oracle_setup(wl)
+    assert np.abs(S - S_ref).max() <= 1e-13 * np.abs(S_ref).max()
+
+
+def test_sigma_build_time_dependent_interaction(device):
+    wl = W.config(5)
+    B = _B()
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = _np(B.sigma_build(prob, V, U))
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta)
+    eps = O.site_levels(wl.V, wl.U, wl.mu)
+    for i in [0, 17, 528, 1023]:
+        ref = O.atomic_gf(eps[i], wl.U, c)
+        assert np.abs(S[i] - ref).max() <= 1e-13, i
+
+
+def _solve(wl, device, sources, block_sites, want_cols=True, tol=1e-13, max_iter=400):
+    B = _B()
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = B.sigma_build(prob, V, U)
+    out = B.dyson_iterate(prob, S, J, sources, block_sites=block_sites, tol=tol,
+                          max_iter=max_iter, want_cols=want_cols)
+    n, ek = B.local_observables(prob, out["G_loc"], out["G_nn"], J)
+    return prob, out, _np(n), _np(ek)
+
+
+@pytest.mark.parametrize("wl,block", [
+    (W.config(1), 16),
+    (W.custom(3, 5, 7, 5, J0=0.08, seed=4), 4),              # N_t = 19: padded tiles, ragged blocks
+    (W.custom(4, 3, 6, 4, J0=0.1, periodic=True, seed=6), 5),
+    (W.custom(5, 1, 9, 6, J0=0.12, seed=12), 2),
+], ids=["cfg1", "ragged3x5", "periodic4x3", "chain5"])
+def test_dyson_full_matches_dense_oracle(wl, block, device):
+    c, S_ref, G = oracle_dense(wl)
+    sources = list(range(wl.n_r))[::-1]                       # reversed order: block bookkeeping
+    prob, out, n, ek = _solve(wl, device, sources, block)
+    cols_ref = dense_columns(G, wl.n_r, c.n_t, sources)
+    assert rel_maxnorm(_np(out["G_cols"]), cols_ref) <= 1e-12
+    nbr = O.neighbours(wl.Lx, wl.Ly, wl.periodic)
+    G_loc = O.local_blocks_from_dense(G, c.n_t, sources)
+    G_nn = O.neighbour_blocks_from_dense(G, c.n_t, nbr, sources)
+    assert rel_maxnorm(_np(out["G_loc"]), G_loc) <= 1e-12
+    assert rel_maxnorm(_np(out["G_nn"]), G_nn) <= 1e-12
+    assert np.abs(n - O.occupancy(G_loc, c)).max() <= 1e-12
+    assert np.abs(ek - O.kinetic_energy(G_nn, nbr[sources], wl.J, c)).max() <= 1e-12
+    st = out["stats"]
+    assert st["status"] == 0 and st["n_blocks"] == -(-wl.n_r // block)
+
+
+def test_zero_hopping_returns_sigma_after_one_sweep(device):
+    wl = W.custom(3, 4, 5, 4, J0=0.0, seed=2)
+    from paper_1309_5994_amd import scdyson as B
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = B.sigma_build(prob, V, U)
+    out = B.dyson_iterate(prob, S, J, list(range(wl.n_r)), block_sites=12, tol=1e-13)
+    assert np.abs(_np(out["G_loc"]) - _np(S)).max() == 0.0          # G = S exactly
+    _, S_ref = oracle_setup(wl)
+    assert np.abs(_np(S) - S_ref).max() <= 1e-13
+    assert out["stats"]["sweeps_max"] == 1
+    assert np.abs(_np(out["G_nn"])).max() == 0.0
+
+
+def test_config4_all_sites_against_golden(device):
+    gold = np.load(__import__("os").path.join(__import__("os").path.dirname(__file__),
+                                              "golden", "cfg4.npz"))
+    wl = W.config(4)
+    prob, out, n, ek = _solve(wl, device, list(range(wl.n_r)), wl.n_r, want_cols=False, tol=1e-13)
+    assert np.abs(n - gold["n_all"]).max() <= 1e-12
+    assert np.abs(ek - gold["ekin_all"]).max() <= 1e-12
+    src = [int(s) for s in gold["sources"]]
+    G_loc = _np(out["G_loc"])[src]
+    for s in range(len(src)):
+        ref = gold["loc_re"][s] + 1j * gold["loc_im"][s]
+        got = G_loc[s][gold["loc_a"][s], gold["loc_b"][s]]
+        assert np.abs(got - ref).max() <= 1e-12 * gold["G_absmax"][0]
+
+
+def _golden_columns_check(k, device, block_sites, extra_fill=True):
+    import os
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", f"cfg{k}.npz"))
+    wl = W.config(k)
+    src = [int(s) for s in gold["sources"]]
+    # Run the sampled sources inside a full block (the benchmark's launch shape),
+    # padding the block with further seeded sources.
+    rng = np.random.default_rng(77)
+    pool = [s for s in rng.permutation(wl.n_r).tolist() if s not in src]
+    block = src + (pool[:max(0, block_sites - len(src))] if extra_fill else [])
+    prob, out, n, ek = _solve(wl, device, block, block_sites, want_cols=True, tol=1e-13,
+                              max_iter=600)
+    n_t = wl.n_t
+    ns = len(src)
+    assert np.abs(n[:ns] - gold["n"]).max() <= 1e-12
+    assert np.abs(ek[:ns] - gold["ekin"]).max() <= 1e-12
+    gmax = gold["G_absmax"][0]
+    G_loc = _np(out["G_loc"])
+    for s in range(ns):
+        ref = gold["loc_re"][s] + 1j * gold["loc_im"][s]
+        got = G_loc[s][gold["loc_a"][s], gold["loc_b"][s]]
+        assert np.abs(got - ref).max() <= 1e-12 * gmax, s
+    cols = out["G_cols"]
+    # Gather the sampled entries on the device instead of copying whole columns.
+    import torch
+    for s in range(ns):
+        site = torch.as_tensor(gold["sample_site"][s], device=cols.device)
+        a = torch.as_tensor(gold["sample_a"][s], device=cols.device)
+        b = torch.as_tensor(gold["sample_b"][s] + s * n_t, device=cols.device)
+        got = _np(cols[site, a, b])
+        exp = gold["sample_re"][s] + 1j * gold["sample_im"][s]
+        assert np.abs(got - exp).max() <= 1e-12 * gmax, s
+    return out
+
+
+def test_config2_full_block_sampled_columns(device):
+    out = _golden_columns_check(2, device, 256)
+    assert out["stats"]["status"] == 0
+
+
+def test_deterministic_bitwise(device):
+    import torch
+    wl = W.custom(4, 4, 8, 6, J0=0.1, seed=21)
+    _, a, _, _ = _solve(wl, device, list(range(16)), 7)
+    _, b, _, _ = _solve(wl, device, list(range(16)), 7)
+    assert torch.equal(a["G_cols"], b["G_cols"])

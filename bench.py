@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, help="named workload 1..5")
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -79,6 +81,13 @@ def main():
     outs = {"G_loc": torch.empty((wl.n_r, n_t, n_t), dtype=torch.complex128, device=dev),
             "G_nn": torch.empty((wl.n_r, 4, n_t, n_t), dtype=torch.complex128, device=dev)}
     ws = torch.empty(B.workspace_bytes(prob, len(src), block), dtype=torch.uint8, device=dev)
+
+    if args.copy_calib:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def step():
         B.sigma_build(prob, V, U, S)

@@ -113,6 +113,21 @@ struct EventPair {
     }
 };
 
+// Sites per tile-order group of the sweep kernel (see tile_site_col):
+// SCD_SITE_GROUP overrides; the default keeps a group's site operands
+// (mp^2 complex each) within about 2 MB of one XCD's L2.
+int site_group(const Geom& g) {
+    if (const char* env = std::getenv("SCD_SITE_GROUP")) {
+        const int v = std::atoi(env);
+        if (v >= 1) return v < g.n_r ? v : g.n_r;
+    }
+    const double per_site = (double)g.mp * g.mp * 16.0;
+    int grp = (int)(2.0e6 / per_site);
+    if (grp < 1) grp = 1;
+    if (grp > g.n_r) grp = g.n_r;
+    return grp;
+}
+
 double bits_to_double(unsigned long long u) {
     double d;
     std::memcpy(&d, &u, sizeof d);
@@ -232,6 +247,7 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         a.ntn = L.ntn;
         a.bs = bs;
         a.lc_sweep = 0;
+        a.group = site_group(g);
         // Pairs (target, source) by lattice distance: sweep n reaches distance n.
         std::vector<double> within(g.Lx + g.Ly + 1, 0.0);
         for (int s = 0; s < bs; ++s) {

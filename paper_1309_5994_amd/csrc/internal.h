@@ -16,6 +16,7 @@ constexpr int kMaxRowTiles = 16;
 constexpr int kMaxNt = kTile * kMaxRowTiles;     // 256
 constexpr int kColsPerWG = 64;                   // column tile of one sweep workgroup
 
+typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 
@@ -38,7 +39,21 @@ struct SweepArgs {
     int ntn;        // column tiles per site = ldx / 64
     int bs;         // source sites in this block
     int lc_sweep;   // sweeps already applied (light cone radius) or -1 to disable skipping
+    int group;      // tile order: groups of `group` consecutive sites, column tile major inside
 };
+
+// Logical tile -> (site, column tile).  Sites are taken in groups of `group`
+// consecutive sites; inside a group the column tile is the slow index, so the
+// workgroups that run together share neighbour tiles of the iterate.
+__host__ __device__ inline void tile_site_col(int tile, int ntn, int n_r, int group, int* site,
+                                              int* ct) {
+    const int g = tile / (group * ntn);
+    const int first = g * group;
+    const int cnt = (n_r - first) < group ? (n_r - first) : group;
+    const int local = tile - first * ntn;
+    *ct = local / cnt;
+    *site = first + (local - (local / cnt) * cnt);
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

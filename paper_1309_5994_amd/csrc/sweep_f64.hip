@@ -44,8 +44,10 @@ void sweep_f64_kernel(const double2* __restrict__ St, const double2* __restrict_
     constexpr int B_PER = (B_ELEMS + kThreads - 1) / kThreads;
     static_assert(MP % KC == 0, "k chunk must divide the padded contour length");
 
-    __shared__ double2 As[A_ELEMS];   // [KC][MP]
-    __shared__ double2 Bs[B_ELEMS];   // [KC][NW]
+    static_assert(B_ELEMS % kThreads == 0, "B chunk must be a whole number of passes");
+    // Native vector types (not HIP_vector_type) keep the staging arrays in registers.
+    __shared__ dvec2 As[A_PER * kThreads];   // [KC][MP] + padding of the last pass
+    __shared__ dvec2 Bs[B_ELEMS];            // [KC][NW]
     __shared__ double red[kThreads / 64][3];
 
     const int tid = threadIdx.x;
@@ -57,8 +59,9 @@ void sweep_f64_kernel(const double2* __restrict__ St, const double2* __restrict_
     const int lq = lane >> 4;
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    const int i = tile / g.ntn;
-    const int n0 = (tile - i * g.ntn) * NW;
+    int i, ct;
+    tile_site_col(tile, g.ntn, g.n_r, g.group, &i, &ct);
+    const int n0 = ct * NW;
     const int ldx = g.ldx;
 
     int nb[4];
@@ -92,9 +95,10 @@ void sweep_f64_kernel(const double2* __restrict__ St, const double2* __restrict_
         }
     }
 
-    const double2* Sti = St + (size_t)i * MP * MP;
-    const double2* Xk[4];
-    for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * ldx : nullptr;
+    const dvec2* Sti = reinterpret_cast<const dvec2*>(St) + (size_t)i * MP * MP;
+    const dvec2* Xk[4];
+    for (int d = 0; d < 4; ++d)
+        Xk[d] = nb[d] >= 0 ? reinterpret_cast<const dvec2*>(X) + (size_t)nb[d] * MP * ldx : nullptr;
 
     dvec4 accr[MH], acci[MH];
 #pragma unroll
@@ -105,56 +109,46 @@ void sweep_f64_kernel(const double2* __restrict__ St, const double2* __restrict_
     const int t0 = grp ? MH : 0;
     const int ntile = grp ? MT - MH : MH;
 
-    double2 ra[A_PER];
-    double2 rb[B_PER][4];
+    dvec2 ra[A_PER];
+    dvec2 rb[B_PER][4];
 
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int r = 0; r < A_PER; ++r) {
-            const int e = tid + r * kThreads;
-            if (A_ELEMS % kThreads == 0 || e < A_ELEMS) ra[r] = Sti[(size_t)k0 * MP + e];
-        }
-#pragma unroll
-        for (int r = 0; r < B_PER; ++r) {
-            const int e = tid + r * kThreads;
-            const int kk = e / NW, col = e - (e / NW) * NW;
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-                rb[r][d] = make_double2(0.0, 0.0);
-                if ((B_ELEMS % kThreads == 0 || e < B_ELEMS) && Xk[d])
-                    rb[r][d] = Xk[d][(size_t)(k0 + kk) * ldx + n0 + col];
-            }
-        }
-    };
-    auto lstore = [&]() {
-#pragma unroll
-        for (int r = 0; r < A_PER; ++r) {
-            const int e = tid + r * kThreads;
-            if (A_ELEMS % kThreads == 0 || e < A_ELEMS) As[e] = ra[r];
-        }
-#pragma unroll
-        for (int r = 0; r < B_PER; ++r) {
-            const int e = tid + r * kThreads;
-            if (B_ELEMS % kThreads == 0 || e < B_ELEMS) {
-                double2 s;
-                s.x = (rb[r][0].x + rb[r][1].x) + (rb[r][2].x + rb[r][3].x);
-                s.y = (rb[r][0].y + rb[r][1].y) + (rb[r][2].y + rb[r][3].y);
-                Bs[e] = s;
-            }
-        }
-    };
+    // Staging of one K chunk: global -> registers (issued a chunk ahead) and
+    // registers -> LDS.  Threads past the end of the A chunk re-load its last
+    // element into LDS padding, so no lane is predicated off.
+#define SCD_GLOAD(k0)                                                                  \
+    do {                                                                               \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) {                            \
+            int e = tid + r * kThreads;                                                \
+            e = e < A_ELEMS ? e : A_ELEMS - 1;                                         \
+            ra[r] = Sti[(size_t)(k0) * MP + e];                                        \
+        }                                                                              \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r) {                            \
+            const int e = tid + r * kThreads;                                          \
+            const int kk = e / NW, col = e - (e / NW) * NW;                            \
+            const size_t off = (size_t)((k0) + kk) * ldx + n0 + col;                   \
+            _Pragma("unroll") for (int d = 0; d < 4; ++d)                              \
+                rb[r][d] = Xk[d] ? Xk[d][off] : dvec2{0.0, 0.0};                       \
+        }                                                                              \
+    } while (0)
+#define SCD_LSTORE()                                                                   \
+    do {                                                                               \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) As[tid + r * kThreads] = ra[r]; \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r) {                            \
+            Bs[tid + r * kThreads] = (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);    \
+        }                                                                              \
+    } while (0)
 
-    gload(0);
+    SCD_GLOAD(0);
     for (int k0 = 0; k0 < MP; k0 += KC) {
         __syncthreads();
-        lstore();
+        SCD_LSTORE();
         __syncthreads();
-        if (k0 + KC < MP) gload(k0 + KC);
+        if (k0 + KC < MP) SCD_GLOAD(k0 + KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             const int kr = 4 * s + lq;
-            const double2 b = Bs[kr * NW + wc * 16 + l16];
-            double2 a[MH];
+            const dvec2 b = Bs[kr * NW + wc * 16 + l16];
+            dvec2 a[MH];
 #pragma unroll
             for (int t = 0; t < MH; ++t)
                 if (t < ntile) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
@@ -224,6 +218,8 @@ void sweep_f64_kernel(const double2* __restrict__ St, const double2* __restrict_
         for (int w = 0; w < kThreads / 64; ++w) m = fmax(m, red[w][tid]);
         partial[3 * blockIdx.x + tid] = m;
     }
+#undef SCD_GLOAD
+#undef SCD_LSTORE
 }
 
 template <int MT>

@@ -84,9 +84,10 @@ typedef struct scd_stats {
     double  gemm_flops;     /* algorithmic contour-GEMM flops: 8 N_t^3 per (target, source)
                                pair inside the sweep's light cone (8 flops per complex MAC) */
     double  seconds;        /* host wall time of the call                       */
-    double  sweep_kernel_seconds; /* summed HIP-event time of the sweep kernels  */
-    int32_t sweep_launches; /* sweep-kernel launches timed                      */
-    int32_t reserved;
+    double  sweep_kernel_seconds; /* summed HIP-event time of the FP64 sweep kernels */
+    double  lowp_kernel_seconds;  /* summed HIP-event time of the FP32 correction sweeps */
+    int32_t sweep_launches; /* FP64 sweep-kernel launches timed                 */
+    int32_t lowp_launches;  /* FP32 correction-sweep launches timed             */
 } scd_stats;
 
 /*

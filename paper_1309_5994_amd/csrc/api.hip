@@ -73,22 +73,40 @@ int check_problem(const scd_problem* p, int max_nt, Geom* g) {
 
 struct Layout {
     int ldx, ntn, nwg;
-    size_t off_st, off_x0, off_x1, off_partial, off_slot, off_src, total;
+    size_t off_st, off_st32, off_x0, off_x1, off_r32, off_d0, off_d1, off_partial, off_slot,
+        off_src, total;
 };
 
-Layout layout(const Geom& g, int n_src, int block_sites) {
+// Workspace: St (FP64 operand), two FP64 iterates (FP64 path) or one FP64
+// iterate + St32 + residual and two corrections in complex64 (FP32 path).
+Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
     Layout L;
     const int bs = block_sites < n_src ? block_sites : n_src;
     L.ldx = ((bs * g.n_t + kColsPerWG - 1) / kColsPerWG) * kColsPerWG;
     L.ntn = L.ldx / kColsPerWG;
     L.nwg = g.n_r * L.ntn;
+    const size_t it64 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
+    const size_t it32 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(float2));
     size_t off = 0;
     L.off_st = off;
     off += align256((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
     L.off_x0 = off;
-    off += align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
-    L.off_x1 = off;
-    off += align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
+    off += it64;
+    if (prec == SCD_PREC_FP64) {
+        L.off_x1 = off;
+        off += it64;
+        L.off_st32 = L.off_r32 = L.off_d0 = L.off_d1 = 0;
+    } else {
+        L.off_x1 = 0;
+        L.off_st32 = off;
+        off += align256((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
+        L.off_r32 = off;
+        off += it32;
+        L.off_d0 = off;
+        off += it32;
+        L.off_d1 = off;
+        off += it32;
+    }
     L.off_partial = off;
     off += align256((size_t)L.nwg * 3 * sizeof(double));
     L.off_slot = off;
@@ -134,6 +152,208 @@ double bits_to_double(unsigned long long u) {
     return d;
 }
 
+struct BlockResult {
+    double2* X = nullptr;   // buffer holding the final iterate
+    int sweeps = 0;
+    double err = 0.0, rho = 0.0;
+};
+
+// Host side of the sweep loops of one column block.
+struct Solver {
+    Geom g;
+    hipStream_t st;
+    scd_stats* stats;
+    double2* St;
+    void* St32;
+    const double2* S;
+    double* partial;
+    unsigned long long* slot;
+    int nwg;
+    EventPair ev;
+    std::vector<double> within;   // (target, source) pairs within lattice distance d, cumulative
+
+    void pair_counts(const int32_t* src_host, int bs) {
+        within.assign(g.Lx + g.Ly + 1, 0.0);
+        for (int s = 0; s < bs; ++s) {
+            const int j = src_host[s];
+            const int xj = j / g.Ly, yj = j % g.Ly;
+            for (int i = 0; i < g.n_r; ++i) {
+                int dx = std::abs(i / g.Ly - xj), dy = std::abs(i % g.Ly - yj);
+                if (g.periodic) {
+                    dx = std::min(dx, g.Lx - dx);
+                    dy = std::min(dy, g.Ly - dy);
+                }
+                within[dx + dy] += 1.0;
+            }
+        }
+        for (size_t d = 1; d < within.size(); ++d) within[d] += within[d - 1];
+    }
+    // Algorithmic flops of a sweep whose output reaches lattice distance `radius`.
+    double sweep_flops(int radius, int cols_per_src) const {
+        const size_t last = within.size() - 1;
+        const double pairs = within[(size_t)radius < last ? (size_t)radius : last];
+        return 8.0 * g.n_t * (double)g.n_t * (double)cols_per_src * pairs;
+    }
+    // Fold the per-workgroup partials of the last sweep; returns SCD_OK or SCD_EHIP.
+    int reduce(double out[3]) {
+        SCD_HIP(hipMemsetAsync(slot, 0, 4 * sizeof(unsigned long long), st), "slot clear");
+        SCD_HIP(launch_reduce_max3(partial, nwg, slot, st), "reduce launch");
+        unsigned long long h[3];
+        SCD_HIP(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st), "slot copy");
+        SCD_HIP(hipStreamSynchronize(st), "sweep sync");
+        for (int q = 0; q < 3; ++q) out[q] = bits_to_double(h[q]);
+        return SCD_OK;
+    }
+    int elapsed(double* seconds) {
+        float ms = 0.0f;
+        SCD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b), "event time");
+        *seconds = 1e-3 * ms;
+        return SCD_OK;
+    }
+
+    // Plain FP64 Jacobi sweeps X <- X0 + St^T N(X) until the relative increment
+    // and its contraction-corrected error estimate are below tol.
+    int solve_fp64(SweepArgs a, const int* src_blk, double2* X, double2* Xn, double tol,
+                   int max_iter, BlockResult* res) {
+        const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
+        double e_prev = 0.0, d_prev = 0.0, rho = 0.0, e_n = 0.0;
+        int grow = 0, n = 0, code = SCD_ENOTCONV;
+        double2* cur = X;
+        double2* nxt = Xn;
+        for (n = 1; n <= max_iter; ++n) {
+            a.lc_sweep = a.lc_sweep < 0 ? -1 : n - 1;
+            SCD_HIP(hipEventRecord(ev.a, st), "event record");
+            SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, cur, nxt, partial, st), "sweep launch");
+            SCD_HIP(hipEventRecord(ev.b, st), "event record");
+            double r[3], secs;
+            if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
+            std::swap(cur, nxt);
+            stats->fp64_sweeps++;
+            stats->sweep_launches++;
+            stats->sweep_kernel_seconds += secs;
+            stats->gemm_flops += sweep_flops(a.lc_sweep < 0 ? 1 << 20 : n, cps);
+            if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
+                code = fail(SCD_ENAN, "NaN or Inf in the iterate at sweep %d", n);
+                break;
+            }
+            e_n = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+            if (n >= 2 && e_prev > 0.0) rho = e_n / e_prev;
+            if (e_n == 0.0) {
+                code = SCD_OK;
+                break;
+            }
+            if (e_n <= tol && n >= 2 &&
+                (e_n <= 1e-2 * tol || (rho < 1.0 && e_n * rho / (1.0 - rho) <= tol))) {
+                code = SCD_OK;
+                break;
+            }
+            // A convergent Dyson series has shrinking increments; a divergent one
+            // grows them geometrically (the relative increment stays O(1)).
+            grow = (n >= 2 && r[0] > d_prev) ? grow + 1 : 0;
+            if (grow >= 8) {
+                code = fail(SCD_EDIVERGED,
+                            "sweep increments grew 8 times in a row (|dX|=%g, sweep %d)", r[0], n);
+                break;
+            }
+            e_prev = e_n;
+            d_prev = r[0];
+        }
+        res->X = cur;
+        res->sweeps = n > max_iter ? max_iter : n;
+        res->err = e_n;
+        res->rho = rho;
+        return code;
+    }
+
+    // Iterative refinement: FP64 residual R = X0 + St^T N(X) - X (complex64
+    // output), FP32-MFMA correction sweeps D <- R + St^T N(D) to a relative
+    // increment of 1e-6 (or stagnation), then X += D in FP64.  Stops when the
+    // relative FP64 residual, divided by (1 - rho), is below tol.
+    int solve_mixed(SweepArgs a, const int* src_blk, double2* X, void* R32, void* D0, void* D1,
+                    double tol, int max_iter, BlockResult* res) {
+        const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
+        const size_t n_elem = (size_t)g.n_r * g.mp * a.ldx;
+        const size_t bytes32 = n_elem * sizeof(float2);
+        SCD_HIP(hipMemsetAsync(R32, 0, bytes32, st), "clear");
+        SCD_HIP(hipMemsetAsync(D0, 0, bytes32, st), "clear");
+        SCD_HIP(hipMemsetAsync(D1, 0, bytes32, st), "clear");
+        const bool cone = a.lc_sweep >= 0;
+        int radius_x = 0;           // lattice distance the iterate reaches
+        double rho = 0.0, e_r = 0.0, d_prev = 0.0;
+        int outer = 0, code = SCD_ENOTCONV, grow = 0;
+        const int max_inner = 1000;
+        const double inner_tol = 1e-6;
+        for (outer = 1; outer <= max_iter; ++outer) {
+            a.lc_sweep = cone ? radius_x : -1;
+            SCD_HIP(hipEventRecord(ev.a, st), "event record");
+            SCD_HIP(launch_residual_f64(g, a, St, S, src_blk, X, R32, partial, st),
+                    "residual launch");
+            SCD_HIP(hipEventRecord(ev.b, st), "event record");
+            double r[3], secs;
+            if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
+            stats->fp64_sweeps++;
+            stats->sweep_launches++;
+            stats->sweep_kernel_seconds += secs;
+            stats->gemm_flops += sweep_flops(cone ? radius_x + 1 : 1 << 20, cps);
+            if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
+                code = fail(SCD_ENAN, "NaN or Inf in the FP64 residual at refinement step %d",
+                            outer);
+                break;
+            }
+            e_r = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+            if (e_r == 0.0 || (outer >= 2 && rho < 1.0 && e_r / (1.0 - rho) <= tol)) {
+                code = SCD_OK;
+                break;
+            }
+            grow = (outer >= 2 && r[0] > d_prev) ? grow + 1 : 0;
+            if (grow >= 3) {
+                code = fail(SCD_EDIVERGED, "FP64 residual grew 3 refinement steps in a row (%g)",
+                            r[0]);
+                break;
+            }
+            d_prev = r[0];
+            if (outer == max_iter) break;
+            // Correction sweeps from D_0 = R.
+            const int radius_r = radius_x + 1;
+            SCD_HIP(launch_copy_f32(R32, D0, n_elem, st), "copy launch");
+            void* dc = D0;
+            void* dn = D1;
+            double e_prev = 0.0;
+            int j = 0, stall = 0;
+            for (j = 1; j <= max_inner; ++j) {
+                a.lc_sweep = cone ? radius_r + j - 1 : -1;
+                SCD_HIP(hipEventRecord(ev.a, st), "event record");
+                SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, dc, dn, partial, st),
+                        "correct launch");
+                SCD_HIP(hipEventRecord(ev.b, st), "event record");
+                if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
+                std::swap(dc, dn);
+                stats->lowp_sweeps++;
+                stats->lowp_launches++;
+                stats->lowp_kernel_seconds += secs;
+                stats->gemm_flops += sweep_flops(cone ? radius_r + j : 1 << 20, cps);
+                if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
+                    code = fail(SCD_ENAN, "NaN or Inf in an FP32 correction sweep");
+                    break;
+                }
+                const double e_in = r[1] > 0.0 ? r[0] / r[1] : 0.0;
+                if (j >= 2 && e_prev > 0.0 && e_in < e_prev) rho = e_in / e_prev;
+                stall = (j >= 2 && e_in >= e_prev) ? stall + 1 : 0;
+                e_prev = e_in;
+                if (e_in <= inner_tol || stall >= 3) break;
+            }
+            if (code == SCD_ENAN) break;
+            SCD_HIP(launch_axpy_f32_to_f64(X, dc, n_elem, st), "axpy launch");
+            radius_x = radius_r + (j > max_inner ? max_inner : j);
+        }
+        res->X = X;
+        res->sweeps = outer > max_iter ? max_iter : outer;
+        res->err = e_r;
+        res->rho = rho;
+        return code;
+    }
+};
+
 }  // namespace
 
 extern "C" {
@@ -148,8 +368,9 @@ int scd_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites
     if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
     if (n_src < 1 || n_src > g.n_r) return fail(SCD_EINVAL, "n_src must be in [1, N_r]");
     if (block_sites < 1) return fail(SCD_EINVAL, "block_sites must be >= 1");
-    if (prec != SCD_PREC_FP64) return fail(SCD_EINVAL, "unsupported precision %d", prec);
-    *bytes = layout(g, n_src, block_sites).total;
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+        return fail(SCD_EINVAL, "unsupported precision %d", prec);
+    *bytes = layout(g, n_src, block_sites, prec).total;
     g_last_error.clear();
     return SCD_OK;
 }
@@ -204,32 +425,38 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         return finish(fail(SCD_EINVAL, "S, J, src, G_loc and ws must be non-NULL"));
     if (n_src < 1 || n_src > g.n_r) return finish(fail(SCD_EINVAL, "n_src must be in [1, N_r]"));
     if (block_sites < 1) return finish(fail(SCD_EINVAL, "block_sites must be >= 1"));
-    if (prec != SCD_PREC_FP64) return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+        return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
     if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
     if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
     for (int s = 0; s < n_src; ++s)
         if (src[s] < 0 || src[s] >= g.n_r)
             return finish(fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r));
-    const Layout L = layout(g, n_src, block_sites);
+    const Layout L = layout(g, n_src, block_sites, prec);
     if (ws_bytes < L.total)
         return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total));
 
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
-    double2* St = (double2*)(base + L.off_st);
-    double2* Xa = (double2*)(base + L.off_x0);
-    double2* Xb = (double2*)(base + L.off_x1);
-    double* partial = (double*)(base + L.off_partial);
-    unsigned long long* slot = (unsigned long long*)(base + L.off_slot);
+    Solver sv;
+    sv.g = g;
+    sv.st = st;
+    sv.stats = &stats;
+    sv.St = (double2*)(base + L.off_st);
+    sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + L.off_st32) : nullptr;
+    sv.S = (const double2*)S;
+    sv.partial = (double*)(base + L.off_partial);
+    sv.slot = (unsigned long long*)(base + L.off_slot);
+    sv.nwg = L.nwg;
     int* src_dev = (int*)(base + L.off_src);
 
     SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
             "copy src");
-    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, St, st), "scale_transpose launch");
+    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, st), "scale_transpose launch");
+    if (sv.St32)
+        SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
-    EventPair evs;
-    SCD_HIP(evs.create(), "event create");
-    hipEvent_t ev0 = evs.a, ev1 = evs.b;
+    SCD_HIP(sv.ev.create(), "event create");
 
     const int bs_max = block_sites < n_src ? block_sites : n_src;
     double worst_err = 0.0, worst_rho = 0.0;
@@ -248,90 +475,32 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         a.bs = bs;
         a.lc_sweep = 0;
         a.group = site_group(g);
-        // Pairs (target, source) by lattice distance: sweep n reaches distance n.
-        std::vector<double> within(g.Lx + g.Ly + 1, 0.0);
-        for (int s = 0; s < bs; ++s) {
-            const int j = src[blk_start + s];
-            const int xj = j / g.Ly, yj = j % g.Ly;
-            for (int i = 0; i < g.n_r; ++i) {
-                int dx = std::abs(i / g.Ly - xj), dy = std::abs(i % g.Ly - yj);
-                if (g.periodic) {
-                    dx = std::min(dx, g.Lx - dx);
-                    dy = std::min(dy, g.Ly - dy);
-                }
-                within[dx + dy] += 1.0;
-            }
-        }
-        for (size_t d = 1; d < within.size(); ++d) within[d] += within[d - 1];
-        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, Xa, Xb, st),
+        a.x0_kind = X0_BLOCK;
+        a.x0_fixed = 0;
+        sv.pair_counts(src + blk_start, bs);
+        double2* X = (double2*)(base + L.off_x0);
+        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, X0_BLOCK, 0, X,
+                                  prec == SCD_PREC_FP64 ? (double2*)(base + L.off_x1) : nullptr,
+                                  st),
                 "init_block launch");
-        double2* cur = Xa;
-        double2* nxt = Xb;
-        double e_prev = 0.0, rho = 0.0, e_n = 0.0, d_prev = 0.0;
-        int grow = 0, n = 0, code = SCD_ENOTCONV;
-        for (n = 1; n <= max_iter; ++n) {
-            a.lc_sweep = n - 1;
-            SCD_HIP(hipEventRecord(ev0, st), "event record");
-            SCD_HIP(launch_sweep_f64(g, a, St, (const double2*)S, src_blk, cur, nxt, partial, st),
-                    "sweep launch");
-            SCD_HIP(hipEventRecord(ev1, st), "event record");
-            SCD_HIP(hipMemsetAsync(slot, 0, 4 * sizeof(unsigned long long), st), "slot clear");
-            SCD_HIP(launch_reduce_max3(partial, L.nwg, slot, st), "reduce launch");
-            unsigned long long h[3];
-            SCD_HIP(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st), "slot copy");
-            SCD_HIP(hipStreamSynchronize(st), "sweep sync");
-            double2* tmp = cur;
-            cur = nxt;
-            nxt = tmp;
-            stats.fp64_sweeps++;
-            {
-                const size_t dmax_idx = within.size() - 1;
-                const double pairs = within[(size_t)n < dmax_idx ? (size_t)n : dmax_idx];
-                stats.gemm_flops += 8.0 * g.n_t * (double)g.n_t * (double)g.n_t * pairs;
-                float ms = 0.0f;
-                SCD_HIP(hipEventElapsedTime(&ms, ev0, ev1), "event time");
-                stats.sweep_kernel_seconds += 1e-3 * ms;
-                stats.sweep_launches++;
-            }
-            const double dmax = bits_to_double(h[0]);
-            const double xmax = bits_to_double(h[1]);
-            if (bits_to_double(h[2]) != 0.0 || !std::isfinite(dmax) || !std::isfinite(xmax)) {
-                code = fail(SCD_ENAN, "NaN or Inf in the iterate of block at source %d, sweep %d",
-                            blk_start, n);
-                break;
-            }
-            e_n = xmax > 0.0 ? dmax / xmax : 0.0;
-            if (n >= 2 && e_prev > 0.0) rho = e_n / e_prev;
-            if (e_n == 0.0) {
-                code = SCD_OK;
-                break;
-            }
-            if (e_n <= tol && n >= 2 &&
-                (e_n <= 1e-2 * tol || (rho < 1.0 && e_n * rho / (1.0 - rho) <= tol))) {
-                code = SCD_OK;
-                break;
-            }
-            // A convergent Dyson series has shrinking increments; a divergent one
-            // grows them geometrically (the relative increment stays O(1)).
-            grow = (n >= 2 && dmax > d_prev) ? grow + 1 : 0;
-            if (grow >= 8) {
-                code = fail(SCD_EDIVERGED,
-                            "sweep increments grew 8 times in a row (|dX|=%g, sweep %d)", dmax, n);
-                break;
-            }
-            e_prev = e_n;
-            d_prev = dmax;
+        BlockResult res;
+        int code;
+        if (prec == SCD_PREC_FP64) {
+            code = sv.solve_fp64(a, src_blk, X, (double2*)(base + L.off_x1), tol, max_iter, &res);
+        } else {
+            code = sv.solve_mixed(a, src_blk, X, base + L.off_r32, base + L.off_d0,
+                                  base + L.off_d1, tol, max_iter, &res);
         }
-        if (n > max_iter) n = max_iter;
+        if (code == SCD_EHIP) return finish(code);
         if (code == SCD_ENOTCONV)
             fail(SCD_ENOTCONV, "block at source %d not converged after %d sweeps (e=%g)", blk_start,
-                 max_iter, e_n);
+                 max_iter, res.err);
         stats.n_blocks++;
-        stats.sweeps_total += n;
-        if (n > stats.sweeps_max) stats.sweeps_max = n;
-        worst_err = e_n > worst_err ? e_n : worst_err;
-        worst_rho = rho > worst_rho ? rho : worst_rho;
-        SCD_HIP(launch_extract(g, cur, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
+        stats.sweeps_total += res.sweeps;
+        if (res.sweeps > stats.sweeps_max) stats.sweeps_max = res.sweeps;
+        worst_err = res.err > worst_err ? res.err : worst_err;
+        worst_rho = res.rho > worst_rho ? res.rho : worst_rho;
+        SCD_HIP(launch_extract(g, res.X, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
                                (double2*)G_loc, (double2*)G_nn, st),
                 "extract launch");
         if (code != SCD_OK) {

@@ -37,11 +37,15 @@ void scale_transpose_kernel(const double2* __restrict__ S, const double* __restr
 }
 
 // X = X0 = E_J S (the preconditioned unit-vector bundle of the block): zero
-// except the (j, j) sub-blocks, which hold S_j.  Xn is cleared.
+// except on each source's own site, which holds S_j[:, b] (whole sources),
+// S_j[:, fixed] or S_j[fixed, :] (one column per source).  Xn, if given, is
+// cleared.
 __global__ __launch_bounds__(256)
 void init_block_kernel(const double2* __restrict__ S, const int* __restrict__ src_blk, int bs,
-                       int ldx, double2* __restrict__ X, double2* __restrict__ Xn, Geom g) {
+                       int ldx, int x0_kind, int x0_fixed, double2* __restrict__ X,
+                       double2* __restrict__ Xn, Geom g) {
     const size_t total = (size_t)g.n_r * g.mp * ldx;
+    const int cps = x0_kind == X0_BLOCK ? g.n_t : 1;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int col = (int)(e % ldx);
@@ -49,13 +53,18 @@ void init_block_kernel(const double2* __restrict__ S, const int* __restrict__ sr
         const int a = (int)(r % g.mp);
         const int i = (int)(r / g.mp);
         double2 v = make_double2(0.0, 0.0);
-        const int s = col / g.n_t;
+        const int s = col / cps;
         if (s < bs && a < g.n_t && src_blk[s] == i) {
-            const int b = col - s * g.n_t;
-            v = S[((size_t)i * g.n_t + a) * g.n_t + b];
+            const double2* Si = S + (size_t)i * g.n_t * g.n_t;
+            if (x0_kind == X0_COL_T)
+                v = Si[(size_t)x0_fixed * g.n_t + a];
+            else if (x0_kind == X0_COL)
+                v = Si[(size_t)a * g.n_t + x0_fixed];
+            else
+                v = Si[(size_t)a * g.n_t + (col - s * g.n_t)];
         }
         X[e] = v;
-        Xn[e] = make_double2(0.0, 0.0);
+        if (Xn) Xn[e] = make_double2(0.0, 0.0);
     }
 }
 
@@ -151,7 +160,52 @@ void observables_kernel(const double2* __restrict__ G_loc, const double2* __rest
     }
 }
 
+// Elementwise helpers of mixed-precision refinement.
+__global__ __launch_bounds__(256)
+void to_f32_kernel(const dvec2* __restrict__ in, fvec2* __restrict__ out, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const dvec2 v = in[e];
+        out[e] = fvec2{(float)v.x, (float)v.y};
+    }
+}
+
+__global__ __launch_bounds__(256)
+void copy_f32_kernel(const fvec2* __restrict__ in, fvec2* __restrict__ out, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x)
+        out[e] = in[e];
+}
+
+// X += D: the FP64 iterate absorbs the low-precision correction.
+__global__ __launch_bounds__(256)
+void axpy_kernel(dvec2* __restrict__ X, const fvec2* __restrict__ D, size_t n) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const fvec2 d = D[e];
+        X[e] += dvec2{(double)d.x, (double)d.y};
+    }
+}
+
 }  // namespace
+
+hipError_t launch_to_f32(const double2* in, void* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, st,
+                       reinterpret_cast<const dvec2*>(in), reinterpret_cast<fvec2*>(out), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(copy_f32_kernel, dim3(4096), dim3(256), 0, st,
+                       reinterpret_cast<const fvec2*>(in), reinterpret_cast<fvec2*>(out), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st) {
+    hipLaunchKernelGGL(axpy_kernel, dim3(4096), dim3(256), 0, st, reinterpret_cast<dvec2*>(X),
+                       reinterpret_cast<const fvec2*>(D32), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
                                   hipStream_t st) {
@@ -161,8 +215,9 @@ hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double*
 }
 
 hipError_t launch_init_block(const Geom& g, const double2* S, const int* src_blk, int bs, int ldx,
-                             double2* X, double2* Xn, hipStream_t st) {
-    hipLaunchKernelGGL(init_block_kernel, dim3(4096), dim3(256), 0, st, S, src_blk, bs, ldx, X, Xn, g);
+                             int x0_kind, int x0_fixed, double2* X, double2* Xn, hipStream_t st) {
+    hipLaunchKernelGGL(init_block_kernel, dim3(4096), dim3(256), 0, st, S, src_blk, bs, ldx, x0_kind,
+                       x0_fixed, X, Xn, g);
     return hipGetLastError();
 }
 

@@ -17,6 +17,7 @@ constexpr int kMaxNt = kTile * kMaxRowTiles;     // 256
 constexpr int kColsPerWG = 64;                   // column tile of one sweep workgroup
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec2 __attribute__((ext_vector_type(2)));
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 typedef float fvec4 __attribute__((ext_vector_type(4)));
 
@@ -40,7 +41,15 @@ struct SweepArgs {
     int bs;         // source sites in this block
     int lc_sweep;   // sweeps already applied (light cone radius) or -1 to disable skipping
     int group;      // tile order: groups of `group` consecutive sites, column tile major inside
+    int x0_kind;    // X0_BLOCK, X0_COL or X0_COL_T (what X0 holds on a source's own site)
+    int x0_fixed;   // the fixed contour index of X0_COL / X0_COL_T
 };
+
+// X0 of a column block (the preconditioned unit-vector bundle):
+//  X0_BLOCK  column (s, b) = S_j[:, b] on site j = src[s] (all N_t columns per source)
+//  X0_COL    column s      = S_j[:, fixed]  (one column per source)
+//  X0_COL_T  column s      = S_j[fixed, :]  (one column per source, transposed system)
+enum { X0_BLOCK = 0, X0_COL = 1, X0_COL_T = 2 };
 
 // Logical tile -> (site, column tile).  Sites are taken in groups of `group`
 // consecutive sites; inside a group the column tile is the slow index, so the
@@ -95,10 +104,19 @@ hipError_t launch_sigma_build(const Geom& g, const double* V, const double* U, d
 hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
                                   hipStream_t st);
 hipError_t launch_init_block(const Geom& g, const double2* S, const int* src_blk, int bs, int ldx,
-                             double2* X, double2* Xn, hipStream_t st);
+                             int x0_kind, int x0_fixed, double2* X, double2* Xn, hipStream_t st);
 hipError_t launch_sweep_f64(const Geom& g, const SweepArgs& a, const double2* St, const double2* S,
                             const int* src_blk, const double2* X, double2* Xn, double* partial,
                             hipStream_t st);
+hipError_t launch_residual_f64(const Geom& g, const SweepArgs& a, const double2* St,
+                               const double2* S, const int* src_blk, const double2* X, void* R32,
+                               double* partial, hipStream_t st);
+hipError_t launch_correct_f32(const Geom& g, const SweepArgs& a, const void* St32,
+                              const int* src_blk, const void* R32, const void* D32, void* Dn32,
+                              double* partial, hipStream_t st);
+hipError_t launch_to_f32(const double2* in, void* out, size_t n, hipStream_t st);
+hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st);
+hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st);
 hipError_t launch_reduce_max3(const double* partial, int n, unsigned long long* slot,
                               hipStream_t st);
 hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* src_blk, int bs,

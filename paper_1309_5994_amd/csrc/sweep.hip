@@ -1,0 +1,328 @@
+// One Dyson sweep of a column block, fused with its convergence measure:
+//
+//     Y_i = X0_i + St_i^T * sum_{k in nbr(i)} X_k
+//
+// the Dyson-series step of App. C of arXiv:1309.5994 applied to a bundle of
+// unit vectors (eq. blockedGMRESproblem).  St_i = (S_i diag(w J))^T is the
+// site's scaled atomic Green's function stored transposed (see aux.hip).
+//
+// Work decomposition (gfx950, 64-wide waves):
+//  * one workgroup = one target site i and a 64-column tile of the block
+//    iterate, all mp = 16*MT contour rows; 8 waves: waves 0-3 own the upper
+//    row tiles and waves 4-7 the lower ones, each wave one 16-column slice, so
+//    every SIMD runs all MT row tiles of one slice.
+//  * K loop over contour time c in chunks of KC: the chunk of St_i
+//    (contiguous KC x mp complex) and the sum of the (up to) four neighbour
+//    tiles X_k[c-chunk][64 cols] are staged through LDS; the neighbour sum is
+//    the hopping stencil, done while staging so the summed tile never reaches
+//    HBM.  Global loads of chunk k+1 are issued before the MFMAs of chunk k.
+//  * complex products as four real MFMAs per 16x16x4 block
+//    (re += ar br - ai bi, im += ar bi + ai br) on
+//    V_MFMA_F64_16X16X4_F64 (FP64) or V_MFMA_F32_16X16X4_F32 (FP32).
+//  * light cone: after n sweeps the iterate of source j is zero beyond
+//    Manhattan distance n from j (the support argument of Sec. IV.D); a tile
+//    whose sources are all farther than n+1 from site i is skipped (its output
+//    stays zero).
+//
+// Modes:
+//  * SOLVE     (FP64): X0 from S; writes Y; partials max|Y - X|, max|Y|.
+//  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64; partials
+//              max|R|, max|Y|.  The FP64 residual of iterative refinement.
+//  * CORRECT   (FP32): X0 is a complex64 residual R; X is the correction D;
+//              writes D' = R + St^T (sum of neighbours of D); partials
+//              max|D' - D|, max|D'|.
+// X0 kinds (SOLVE / RESIDUAL): BLOCK = whole sources, column (s, b) holds S_j[:, b]
+// on site j = src[s]; COL = one column per source, S_j[:, fixed]; COL_T = one
+// column per source, S_j[fixed, :] (the transposed system of the adjoint).
+#include "internal.h"
+
+namespace scd {
+namespace {
+
+constexpr int kThreads = 512;
+enum { MODE_SOLVE = 0, MODE_RESIDUAL = 1, MODE_CORRECT = 2 };
+
+struct EngF64 {
+    typedef double real;
+    typedef dvec2 cplx;
+    typedef dvec4 acc;
+    // K chunk (contour points per LDS stage); must divide 16 * MT
+    static constexpr int kc(int) { return 16; }
+    __device__ static acc mma(real a, real b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // V_MFMA_F64_16X16X4_F64 result: element v of lane l is row 4 v + l/16, column l%16.
+    __device__ static int row(int v, int lq) { return 4 * v + lq; }
+};
+
+struct EngF32 {
+    typedef float real;
+    typedef fvec2 cplx;
+    typedef fvec4 acc;
+    static constexpr int kc(int mt) { return mt % 2 == 0 ? 32 : 16; }
+    __device__ static acc mma(real a, real b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // V_MFMA_F32_16X16X4_F32 result: element v of lane l is row 4 (l/16) + v, column l%16.
+    __device__ static int row(int v, int lq) { return 4 * lq + v; }
+};
+
+template <class E, int MT, int MODE>
+__global__ __launch_bounds__(kThreads)
+void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restrict__ S,
+                  const int* __restrict__ src_blk, const typename E::cplx* __restrict__ X,
+                  void* __restrict__ out, const fvec2* __restrict__ R,
+                  double* __restrict__ partial, SweepArgs g) {
+    typedef typename E::real real;
+    typedef typename E::cplx cplx;
+    typedef typename E::acc acc;
+    constexpr int KC = E::kc(MT);
+    constexpr int MP = kTile * MT;
+    constexpr int NW = kColsPerWG;
+    constexpr int MH = (MT + 1) / 2;                 // row tiles of the upper wave group
+    constexpr int A_ELEMS = KC * MP;
+    constexpr int A_PER = (A_ELEMS + kThreads - 1) / kThreads;
+    constexpr int B_ELEMS = KC * NW;
+    constexpr int B_PER = B_ELEMS / kThreads;
+    static_assert(MP % KC == 0, "k chunk must tile the padded contour length");
+    static_assert(B_ELEMS % kThreads == 0, "B chunk must be a whole number of passes");
+
+    // Native vector types (not HIP_vector_type) keep the staging arrays in registers.
+    __shared__ cplx As[A_PER * kThreads];   // [KC][MP] + padding of the last pass
+    __shared__ cplx Bs[B_ELEMS];            // [KC][NW]
+    __shared__ double red[kThreads / 64][3];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int grp = wave >> 2;
+    const int wc = wave & 3;
+    const int l16 = lane & 15;
+    const int lq = lane >> 4;
+
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int i, ct;
+    tile_site_col(tile, g.ntn, g.n_r, g.group, &i, &ct);
+    const int n0 = ct * NW;
+    const int ldx = g.ldx;
+    const int cols_per_src = (g.x0_kind == X0_BLOCK) ? g.n_t : 1;
+
+    int nb[4];
+    site_neighbours(i, g.Lx, g.Ly, g.periodic, nb);
+
+    // Light-cone skip (uniform per workgroup).
+    if (g.lc_sweep >= 0) {
+        const int s_lo = n0 / cols_per_src;
+        int s_hi = (n0 + NW - 1) / cols_per_src;
+        if (s_hi > g.bs - 1) s_hi = g.bs - 1;
+        const int xi = i / g.Ly, yi = i - (i / g.Ly) * g.Ly;
+        int dmin = 1 << 30;
+        for (int s = s_lo; s <= s_hi; ++s) {
+            const int j = src_blk[s];
+            const int xj = j / g.Ly, yj = j - (j / g.Ly) * g.Ly;
+            int dx = xi > xj ? xi - xj : xj - xi;
+            int dy = yi > yj ? yi - yj : yj - yi;
+            if (g.periodic) {
+                dx = dx < g.Lx - dx ? dx : g.Lx - dx;
+                dy = dy < g.Ly - dy ? dy : g.Ly - dy;
+            }
+            dmin = dmin < dx + dy ? dmin : dx + dy;
+        }
+        if (s_lo >= g.bs || dmin > g.lc_sweep + 1) {
+            if (tid < 3) partial[3 * blockIdx.x + tid] = 0.0;
+            return;
+        }
+    }
+
+    const cplx* Sti = St + (size_t)i * MP * MP;
+    const cplx* Xk[4];
+    for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * ldx : nullptr;
+
+    acc accr[MH], acci[MH];
+#pragma unroll
+    for (int t = 0; t < MH; ++t) {
+        accr[t] = acc{0, 0, 0, 0};
+        acci[t] = acc{0, 0, 0, 0};
+    }
+    const int t0 = grp ? MH : 0;
+    const int ntile = grp ? MT - MH : MH;
+
+    cplx ra[A_PER];
+    cplx rb[B_PER][4];
+
+    // Staging of one K chunk: global -> registers (issued a chunk ahead) and
+    // registers -> LDS.  Threads past the end of the A chunk re-load its last
+    // element into LDS padding, so no lane is predicated off.
+#define SCD_GLOAD(k0)                                                                  \
+    do {                                                                               \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) {                            \
+            int e = tid + r * kThreads;                                                \
+            e = e < A_ELEMS ? e : A_ELEMS - 1;                                         \
+            ra[r] = Sti[(size_t)(k0) * MP + e];                                        \
+        }                                                                              \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r) {                            \
+            const int e = tid + r * kThreads;                                          \
+            const int kk = e / NW, col = e - (e / NW) * NW;                            \
+            const size_t off = (size_t)((k0) + kk) * ldx + n0 + col;                   \
+            _Pragma("unroll") for (int d = 0; d < 4; ++d)                              \
+                rb[r][d] = Xk[d] ? Xk[d][off] : cplx{0, 0};                            \
+        }                                                                              \
+    } while (0)
+#define SCD_LSTORE()                                                                   \
+    do {                                                                               \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) As[tid + r * kThreads] = ra[r]; \
+        _Pragma("unroll") for (int r = 0; r < B_PER; ++r)                              \
+            Bs[tid + r * kThreads] = (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);    \
+    } while (0)
+
+    SCD_GLOAD(0);
+    for (int k0 = 0; k0 < MP; k0 += KC) {
+        __syncthreads();
+        SCD_LSTORE();
+        __syncthreads();
+        if (k0 + KC < MP) SCD_GLOAD(k0 + KC);
+#pragma unroll
+        for (int s = 0; s < KC / 4; ++s) {
+            {
+                const int kr = 4 * s + lq;
+                const cplx b = Bs[kr * NW + wc * 16 + l16];
+                cplx a[MH];
+#pragma unroll
+                for (int t = 0; t < MH; ++t)
+                    if (t < ntile) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
+#pragma unroll
+                for (int t = 0; t < MH; ++t) {
+                    if (t < ntile) {
+                        accr[t] = E::mma(a[t].x, b.x, accr[t]);
+                        acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < MH; ++t) {
+                    if (t < ntile) {
+                        accr[t] = E::mma(-a[t].y, b.y, accr[t]);
+                        acci[t] = E::mma(a[t].y, b.x, acci[t]);
+                    }
+                }
+            }
+        }
+    }
+#undef SCD_GLOAD
+#undef SCD_LSTORE
+
+    // Epilogue.
+    const int col = n0 + wc * 16 + l16;
+    const int s_src = col / cols_per_src;
+    const int bcol = col - s_src * cols_per_src;
+    const bool own = (MODE != MODE_CORRECT) && (s_src < g.bs) && (src_blk[s_src] == i);
+    const dvec2* Si = S + (size_t)i * g.n_t * g.n_t;
+    const cplx* Xi = X + (size_t)i * MP * ldx;
+    const size_t site_off = (size_t)i * MP * ldx;
+    double mdiff = 0.0, mabs = 0.0, bad = 0.0;
+#pragma unroll
+    for (int t = 0; t < MH; ++t) {
+        if (t < ntile) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = (t0 + t) * kTile + E::row(v, lq);
+                const size_t off = (size_t)row * ldx + col;
+                double re = (double)accr[t][v], im = (double)acci[t][v];
+                const cplx old = Xi[off];
+                if (MODE == MODE_CORRECT) {
+                    const fvec2 r0 = R[site_off + off];
+                    const float yr = (float)re + r0.x, yi = (float)im + r0.y;
+                    reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{yr, yi};
+                    mdiff = fmax(mdiff, (double)fmaxf(fabsf(yr - (float)old.x), fabsf(yi - (float)old.y)));
+                    mabs = fmax(mabs, (double)fmaxf(fabsf(yr), fabsf(yi)));
+                    if (!(isfinite(yr) && isfinite(yi))) bad = 1.0;
+                } else {
+                    if (own && row < g.n_t) {
+                        dvec2 s0;
+                        if (g.x0_kind == X0_COL_T)
+                            s0 = Si[(size_t)g.x0_fixed * g.n_t + row];
+                        else if (g.x0_kind == X0_COL)
+                            s0 = Si[(size_t)row * g.n_t + g.x0_fixed];
+                        else
+                            s0 = Si[(size_t)row * g.n_t + bcol];
+                        re += s0.x;
+                        im += s0.y;
+                    }
+                    // max-norm over real components: no overflow before a true Inf
+                    const double dr = re - (double)old.x, di = im - (double)old.y;
+                    if (MODE == MODE_SOLVE) {
+                        reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{re, im};
+                    } else {
+                        reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
+                    }
+                    mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
+                    mabs = fmax(mabs, fmax(fabs(re), fabs(im)));
+                    if (!(isfinite(re) && isfinite(im))) bad = 1.0;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        mdiff = fmax(mdiff, __shfl_xor(mdiff, m));
+        mabs = fmax(mabs, __shfl_xor(mabs, m));
+        bad = fmax(bad, __shfl_xor(bad, m));
+    }
+    if (lane == 0) {
+        red[wave][0] = mdiff;
+        red[wave][1] = mabs;
+        red[wave][2] = bad;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double m = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) m = fmax(m, red[w][tid]);
+        partial[3 * blockIdx.x + tid] = m;
+    }
+}
+
+template <class E, int MODE>
+hipError_t launch_mode(const Geom& g, const SweepArgs& a, const void* St, const double2* S,
+                       const int* src_blk, const void* X, void* out, const void* R,
+                       double* partial, hipStream_t st) {
+    dim3 grid(g.n_r * a.ntn);
+    typedef typename E::cplx cplx;
+    const cplx* St_ = reinterpret_cast<const cplx*>(St);
+    const cplx* X_ = reinterpret_cast<const cplx*>(X);
+    const dvec2* S_ = reinterpret_cast<const dvec2*>(S);
+    const fvec2* R_ = reinterpret_cast<const fvec2*>(R);
+    switch (g.mt) {
+#define SCD_CASE(m)                                                                         \
+    case m:                                                                                 \
+        hipLaunchKernelGGL((sweep_kernel<E, m, MODE>), grid, dim3(kThreads), 0, st, St_, S_, \
+                           src_blk, X_, out, R_, partial, a);                              \
+        return hipGetLastError();
+        SCD_CASE(1) SCD_CASE(2) SCD_CASE(3) SCD_CASE(4) SCD_CASE(5) SCD_CASE(6) SCD_CASE(7)
+        SCD_CASE(8) SCD_CASE(9) SCD_CASE(10) SCD_CASE(11) SCD_CASE(12) SCD_CASE(13) SCD_CASE(14)
+        SCD_CASE(15) SCD_CASE(16)
+#undef SCD_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sweep_f64(const Geom& g, const SweepArgs& a, const double2* St, const double2* S,
+                            const int* src_blk, const double2* X, double2* Xn, double* partial,
+                            hipStream_t st) {
+    return launch_mode<EngF64, MODE_SOLVE>(g, a, St, S, src_blk, X, Xn, nullptr, partial, st);
+}
+
+hipError_t launch_residual_f64(const Geom& g, const SweepArgs& a, const double2* St,
+                               const double2* S, const int* src_blk, const double2* X, void* R32,
+                               double* partial, hipStream_t st) {
+    return launch_mode<EngF64, MODE_RESIDUAL>(g, a, St, S, src_blk, X, R32, nullptr, partial, st);
+}
+
+hipError_t launch_correct_f32(const Geom& g, const SweepArgs& a, const void* St32,
+                              const int* src_blk, const void* R32, const void* D32, void* Dn32,
+                              double* partial, hipStream_t st) {
+    return launch_mode<EngF32, MODE_CORRECT>(g, a, St32, nullptr, src_blk, D32, Dn32, R32, partial,
+                                             st);
+}
+
+}  // namespace scd

@@ -43,8 +43,9 @@ class Stats(ctypes.Structure):
                 ("fp64_sweeps", ctypes.c_int32), ("lowp_sweeps", ctypes.c_int32),
                 ("final_err", ctypes.c_double), ("rho_est", ctypes.c_double),
                 ("gemm_flops", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("sweep_kernel_seconds", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sweep_kernel_seconds", ctypes.c_double),
+                ("lowp_kernel_seconds", ctypes.c_double),
+                ("sweep_launches", ctypes.c_int32), ("lowp_launches", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -159,6 +159,44 @@ int local_observables(const scd_problem* p, const void* G_loc, const void* G_nn,
                       const double* J, int32_t n_src, double* n_out, double* ekin_out,
                       void* stream);
 
+/*
+ * Device workspace (bytes) for dyson_adjoint at precision prec.
+ */
+int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* bytes);
+
+/*
+ * Densities at one forward time and the adjoint of a weighted density loss
+ *     L = sum_l w_l n_l(t_e),   n_l(t_e) = Im G[(l, e), (l, b(e))]   (Sec. III.A)
+ * for the Dyson solve G = S + S D G.  With G = (I - S D)^-1 S one needs, per
+ * site l, the forward column g_l = G v_l (v_l: unit vector at (l, b(e))) and
+ * the transposed-system column h_l = G^T u_l = (I - S^T D)^-1 S^T u_l
+ * (u_l: unit vector at (l, e)); both are solved by the same sweep kernels
+ * with one column per site (the forward columns are recomputed, nothing is
+ * stored between calls).  Then
+ *     dL/dS_j = sum_l w_l (u_l + D h_l)_j (v_l + D g_l)_j^T,
+ *     dL/dJ(z_c) = Im w_c sum_l w_l sum_i h_l[(i,c)] sum_{k in nbr(i)} g_l[(k,c)],
+ * chained through the closed form of S (eps_j = V_j - U(t_min)/2 - mu, the
+ * Boltzmann weights and the phase integral of U).  Gradients with respect to
+ * J(t) and U(t) sum every contour point that carries the physical time t.
+ *   S        device complex128[N_r][N_t][N_t] from sigma_build
+ *   V, U     device double[N_r], double[n_real] (inputs of sigma_build; needed for gradients)
+ *   J        device double[n_real]
+ *   w_loss   device double[N_r] loss weights (needed for loss or gradients)
+ *   t_index  forward time index e in [0, n_real)
+ *   prec, tol, max_iter   as for dyson_iterate (applied to both solves)
+ *   n_te     device double[N_r] or NULL: n_l(t_e) for every site
+ *   loss     device double[1] or NULL: L
+ *   dV, dU, dJ  device double[N_r], [n_real], [n_real]: all three, or all NULL
+ *              (then only the forward columns are solved)
+ *   ws       device workspace of scd_adjoint_workspace_bytes() bytes
+ * Errors as dyson_iterate.
+ */
+int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const double* U,
+                  const double* J, const double* w_loss, int32_t t_index, int32_t prec,
+                  double tol, int32_t max_iter, double* n_te, double* loss, double* dV,
+                  double* dU, double* dJ, void* ws, size_t ws_bytes, scd_stats* st,
+                  void* stream);
+
 /* Message for the last failing call on this thread ("" if none). */
 const char* scd_last_error(void);
 

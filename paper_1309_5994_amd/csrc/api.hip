@@ -452,7 +452,7 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
 
     SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
             "copy src");
-    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, st), "scale_transpose launch");
+    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, 0, st), "scale_transpose launch");
     if (sv.St32)
         SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
@@ -513,6 +513,201 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     stats.rho_est = worst_rho;
     if (final_code == SCD_OK) g_last_error.clear();
     return finish(final_code);
+}
+
+// ---- adjoint ---------------------------------------------------------------
+
+namespace {
+
+struct AdjLayout {
+    int ldx, ntn, nwg;
+    size_t off_st, off_stt, off_st32, off_stt32, off_xg, off_xh, off_x1, off_r32, off_d0, off_d1,
+        off_lam, off_rsum, off_csum, off_bz, off_djc, off_partial, off_slot, off_src, total;
+};
+
+AdjLayout adj_layout(const Geom& g, int prec) {
+    AdjLayout L;
+    L.ldx = ((g.n_r + kColsPerWG - 1) / kColsPerWG) * kColsPerWG;
+    L.ntn = L.ldx / kColsPerWG;
+    L.nwg = g.n_r * L.ntn;
+    const size_t op64 = align256((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
+    const size_t op32 = align256((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
+    const size_t it64 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
+    const size_t it32 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(float2));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.off_st = take(op64);
+    L.off_stt = take(op64);
+    L.off_xg = take(it64);
+    L.off_xh = take(it64);
+    L.off_st32 = L.off_stt32 = L.off_x1 = L.off_r32 = L.off_d0 = L.off_d1 = 0;
+    if (prec == SCD_PREC_FP64) {
+        L.off_x1 = take(it64);
+    } else {
+        L.off_st32 = take(op32);
+        L.off_stt32 = take(op32);
+        L.off_r32 = take(it32);
+        L.off_d0 = take(it32);
+        L.off_d1 = take(it32);
+    }
+    L.off_lam = take((size_t)g.n_r * g.n_t * g.n_t * sizeof(double2));
+    L.off_rsum = take((size_t)g.n_r * g.n_t * sizeof(double2));
+    L.off_csum = take((size_t)g.n_r * g.n_t * sizeof(double2));
+    L.off_bz = take((size_t)g.n_r * sizeof(double));
+    L.off_djc = take((size_t)g.n_t * sizeof(double));
+    L.off_partial = take((size_t)L.nwg * 3 * sizeof(double));
+    L.off_slot = take(4 * sizeof(unsigned long long));
+    L.off_src = take((size_t)g.n_r * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+        return fail(SCD_EINVAL, "unsupported precision %d", prec);
+    *bytes = adj_layout(g, prec).total;
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const double* U,
+                  const double* J, const double* w_loss, int32_t t_index, int32_t prec, double tol,
+                  int32_t max_iter, double* n_te, double* loss, double* dV, double* dU, double* dJ,
+                  void* ws, size_t ws_bytes, scd_stats* st_out, void* stream) {
+    const auto t_start = std::chrono::steady_clock::now();
+    scd_stats stats;
+    std::memset(&stats, 0, sizeof stats);
+    auto finish = [&](int code) {
+        stats.status = code;
+        stats.seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (st_out) *st_out = stats;
+        return code;
+    };
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return finish(rc);
+    if (g.n_r > 65535) return finish(fail(SCD_EINVAL, "too many sites"));
+    const bool grads = dV || dU || dJ;
+    if (grads && !(dV && dU && dJ))
+        return finish(fail(SCD_EINVAL, "dV, dU and dJ must be given together"));
+    if (!S || !J || !ws) return finish(fail(SCD_EINVAL, "S, J and ws must be non-NULL"));
+    if (grads && (!V || !U)) return finish(fail(SCD_EINVAL, "gradients need V and U"));
+    if ((grads || loss) && !w_loss) return finish(fail(SCD_EINVAL, "the loss needs w_loss"));
+    if (!grads && !loss && !n_te) return finish(fail(SCD_EINVAL, "nothing to compute"));
+    if (t_index < 0 || t_index >= g.n_real)
+        return finish(fail(SCD_EINVAL, "t_index must be in [0, n_real)"));
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+        return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
+    if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
+    const AdjLayout L = adj_layout(g, prec);
+    if (ws_bytes < L.total)
+        return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total));
+
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    std::vector<int32_t> ident(g.n_r);
+    for (int i = 0; i < g.n_r; ++i) ident[i] = i;
+    int* src_dev = (int*)(base + L.off_src);
+    SCD_HIP(hipMemcpyAsync(src_dev, ident.data(), (size_t)g.n_r * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "copy src");
+    double2* St = (double2*)(base + L.off_st);
+    double2* StT = (double2*)(base + L.off_stt);
+    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, St, 0, st), "operand launch");
+    if (grads) SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, StT, 1, st), "operand launch");
+    if (prec == SCD_PREC_FP32) {
+        const size_t n_op = (size_t)g.n_r * g.mp * g.mp;
+        SCD_HIP(launch_to_f32(St, base + L.off_st32, n_op, st), "St32 launch");
+        if (grads) SCD_HIP(launch_to_f32(StT, base + L.off_stt32, n_op, st), "St32 launch");
+    }
+    SCD_HIP(hipStreamSynchronize(st), "setup sync");
+
+    Solver sv;
+    sv.g = g;
+    sv.st = st;
+    sv.stats = &stats;
+    sv.S = (const double2*)S;
+    sv.partial = (double*)(base + L.off_partial);
+    sv.slot = (unsigned long long*)(base + L.off_slot);
+    sv.nwg = L.nwg;
+    SCD_HIP(sv.ev.create(), "event create");
+    sv.pair_counts(ident.data(), g.n_r);
+
+    const int e = t_index, be = 2 * g.n_real - 1 - t_index;
+    double worst_err = 0.0, worst_rho = 0.0;
+    double2* finals[2] = {nullptr, nullptr};
+    for (int pass = 0; pass < (grads ? 2 : 1); ++pass) {
+        SweepArgs a;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.periodic = g.periodic;
+        a.n_r = g.n_r;
+        a.n_t = g.n_t;
+        a.ldx = L.ldx;
+        a.ntn = L.ntn;
+        a.bs = g.n_r;
+        a.lc_sweep = 0;
+        a.group = site_group(g);
+        a.x0_kind = pass == 0 ? X0_COL : X0_COL_T;
+        a.x0_fixed = pass == 0 ? be : e;
+        sv.St = pass == 0 ? St : StT;
+        sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + (pass == 0 ? L.off_st32 : L.off_stt32))
+                                        : nullptr;
+        double2* X = (double2*)(base + (pass == 0 ? L.off_xg : L.off_xh));
+        SCD_HIP(launch_init_block(g, (const double2*)S, src_dev, g.n_r, L.ldx, a.x0_kind,
+                                  a.x0_fixed, X,
+                                  prec == SCD_PREC_FP64 ? (double2*)(base + L.off_x1) : nullptr, st),
+                "init launch");
+        BlockResult res;
+        int code;
+        if (prec == SCD_PREC_FP64) {
+            code = sv.solve_fp64(a, src_dev, X, (double2*)(base + L.off_x1), tol, max_iter, &res);
+        } else {
+            code = sv.solve_mixed(a, src_dev, X, base + L.off_r32, base + L.off_d0,
+                                  base + L.off_d1, tol, max_iter, &res);
+        }
+        if (code == SCD_ENOTCONV)
+            fail(SCD_ENOTCONV, "%s solve not converged after %d sweeps (e=%g)",
+                 pass == 0 ? "forward" : "transposed", max_iter, res.err);
+        stats.n_blocks++;
+        stats.sweeps_total += res.sweeps;
+        if (res.sweeps > stats.sweeps_max) stats.sweeps_max = res.sweeps;
+        worst_err = std::max(worst_err, res.err);
+        worst_rho = std::max(worst_rho, res.rho);
+        if (code != SCD_OK) return finish(code);
+        // The FP64 path ping-pongs; keep the final iterate where the gradient
+        // kernels expect it.
+        if (res.X != X)
+            SCD_HIP(hipMemcpyAsync(X, res.X, (size_t)g.n_r * g.mp * L.ldx * sizeof(double2),
+                                   hipMemcpyDeviceToDevice, st),
+                    "iterate copy");
+        finals[pass] = X;
+    }
+    SCD_HIP(launch_adjoint_loss(g, L.ldx, e, finals[0], w_loss, n_te, loss, st), "loss launch");
+    if (grads) {
+        SCD_HIP(launch_adjoint_grads(g, L.ldx, e, finals[1], finals[0], V, U, J, w_loss,
+                                     (double2*)(base + L.off_lam), (double2*)(base + L.off_rsum),
+                                     (double2*)(base + L.off_csum), (double*)(base + L.off_bz),
+                                     (double*)(base + L.off_djc), dV, dU, dJ, st),
+                "gradient launch");
+    }
+    SCD_HIP(hipStreamSynchronize(st), "final sync");
+    stats.final_err = worst_err;
+    stats.rho_est = worst_rho;
+    g_last_error.clear();
+    return finish(SCD_OK);
 }
 
 }  // extern "C"

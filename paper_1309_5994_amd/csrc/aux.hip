@@ -6,18 +6,36 @@
 namespace scd {
 namespace {
 
-// St[i][c][a] = S_i[a][c] * w_c J(z_c) with zero padding to mp x mp.
-// The contour weight and hopping of the summed-over time c are folded into the
-// GEMM's left operand once, so a sweep is X' = X0 + St^T (sum of neighbour
-// tiles).  32x32 tiles transposed through LDS keep both sides coalesced.
+// The GEMM's left operand, zero padded to mp x mp:
+//   forward system     St[i][c][a] = S_i[a][c]   w_c J(z_c)   (S_i diag(wJ), transposed)
+//   transposed system  St[i][c][a] = S_i[c][a]   w_c J(z_c)   (S_i^T diag(wJ), transposed)
+// The contour weight and hopping of the summed-over time c are folded in once,
+// so a sweep is X' = X0 + St^T (sum of neighbour tiles).  32x32 tiles go
+// through LDS so both sides stay coalesced.
 __global__ __launch_bounds__(256)
 void scale_transpose_kernel(const double2* __restrict__ S, const double* __restrict__ J,
-                            double2* __restrict__ St, Geom g) {
+                            double2* __restrict__ St, int transposed_system, Geom g) {
     __shared__ double2 tile[32][33];
     const int site = blockIdx.z;
     const int a0 = blockIdx.y * 32, c0 = blockIdx.x * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
     const double2* Si = S + (size_t)site * g.n_t * g.n_t;
+    double2* Sti = St + (size_t)site * g.mp * g.mp;
+    if (transposed_system) {
+        // Row c of S_i scaled by wJ[c], stored as row c of St.
+        for (int r = ty; r < 32; r += 8) {
+            const int c = a0 + r, a = c0 + tx;
+            if (c >= g.mp || a >= g.mp) continue;
+            double2 v = make_double2(0.0, 0.0);
+            if (c < g.n_t && a < g.n_t) {
+                const double2 s = Si[(size_t)c * g.n_t + a];
+                const double2 w = contour_wj(c, g.n_real, g.dt, g.dtau, J);
+                v = make_double2(s.x * w.x - s.y * w.y, s.x * w.y + s.y * w.x);
+            }
+            Sti[(size_t)c * g.mp + a] = v;
+        }
+        return;
+    }
     for (int r = ty; r < 32; r += 8) {
         const int a = a0 + r, c = c0 + tx;
         double2 v = make_double2(0.0, 0.0);
@@ -29,7 +47,6 @@ void scale_transpose_kernel(const double2* __restrict__ S, const double* __restr
         tile[r][tx] = v;
     }
     __syncthreads();
-    double2* Sti = St + (size_t)site * g.mp * g.mp;
     for (int r = ty; r < 32; r += 8) {
         const int c = c0 + r, a = a0 + tx;
         if (c < g.mp && a < g.mp) Sti[(size_t)c * g.mp + a] = tile[tx][r];
@@ -208,9 +225,10 @@ hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStre
 }
 
 hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
-                                  hipStream_t st) {
+                                  int transposed_system, hipStream_t st) {
     dim3 grid((g.mp + 31) / 32, (g.mp + 31) / 32, g.n_r);
-    hipLaunchKernelGGL(scale_transpose_kernel, grid, dim3(256), 0, st, S, J, St, g);
+    hipLaunchKernelGGL(scale_transpose_kernel, grid, dim3(256), 0, st, S, J, St, transposed_system,
+                       g);
     return hipGetLastError();
 }
 

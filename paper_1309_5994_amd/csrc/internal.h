@@ -102,7 +102,7 @@ __device__ inline int xcd_remap(int bid, int nb) {
 hipError_t launch_sigma_build(const Geom& g, const double* V, const double* U, double2* S,
                               hipStream_t st);
 hipError_t launch_scale_transpose(const Geom& g, const double2* S, const double* J, double2* St,
-                                  hipStream_t st);
+                                  int transposed_system, hipStream_t st);
 hipError_t launch_init_block(const Geom& g, const double2* S, const int* src_blk, int bs, int ldx,
                              int x0_kind, int x0_fixed, double2* X, double2* Xn, hipStream_t st);
 hipError_t launch_sweep_f64(const Geom& g, const SweepArgs& a, const double2* St, const double2* S,
@@ -117,6 +117,12 @@ hipError_t launch_correct_f32(const Geom& g, const SweepArgs& a, const void* St3
 hipError_t launch_to_f32(const double2* in, void* out, size_t n, hipStream_t st);
 hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st);
 hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st);
+hipError_t launch_adjoint_grads(const Geom& g, int ldx, int e, const double2* H, const double2* Gc,
+                                const double* V, const double* U, const double* J, const double* w,
+                                double2* Lam, double2* rsum, double2* csum, double* bz, double* djc,
+                                double* dV, double* dU, double* dJ, hipStream_t st);
+hipError_t launch_adjoint_loss(const Geom& g, int ldx, int e, const double2* Gc, const double* w,
+                               double* n_te, double* loss, hipStream_t st);
 hipError_t launch_reduce_max3(const double* partial, int n, unsigned long long* slot,
                               hipStream_t st);
 hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* src_blk, int bs,

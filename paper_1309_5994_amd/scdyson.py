@@ -85,6 +85,12 @@ def lib():
                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
     L.local_observables.restype = ctypes.c_int
     L.local_observables.argtypes = [_P(Problem), _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]
+    L.scd_adjoint_workspace_bytes.restype = ctypes.c_int
+    L.scd_adjoint_workspace_bytes.argtypes = [_P(Problem), ctypes.c_int32, _P(ctypes.c_size_t)]
+    L.dyson_adjoint.restype = ctypes.c_int
+    L.dyson_adjoint.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp, _vp,
+                                _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
     _lib = L
     return L
 
@@ -209,3 +215,91 @@ def local_observables(prob: Problem, G_loc, G_nn, J, want_ekin=True, stream=None
     _check(lib().local_observables(ctypes.byref(prob), _ptr(G_loc), _ptr(G_nn if want_ekin else None),
                                    _ptr(J), n_src, _ptr(n), _ptr(ekin), _stream(stream)))
     return n, ekin
+
+
+def adjoint_workspace_bytes(prob: Problem, prec=PREC_FP64) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_adjoint_workspace_bytes(ctypes.byref(prob), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def dyson_adjoint(prob: Problem, S, V, U, J, w=None, t_index=None, prec=PREC_FP64, tol=1e-12,
+                  max_iter=500, grads=True, want_n=True, ws=None, stream=None):
+    """Densities n_l(t_e) of every site and, with ``grads``, the gradients of
+    L = sum_l w_l n_l(t_e) with respect to V, U(t) and J(t).
+
+    Returns dict(n_te, loss, dV, dU, dJ, stats); t_index defaults to the last
+    forward time.  Raises ScdError on failure."""
+    import torch
+    n_r = prob.n_r
+    _need(S, torch.complex128, (n_r, prob.n_t, prob.n_t), "S")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    if grads:
+        _need(V, torch.float64, (n_r,), "V")
+        _need(U, torch.float64, (prob.n_real,), "U")
+    if w is not None:
+        _need(w, torch.float64, (n_r,), "w")
+    dev = S.device
+    t_index = prob.n_real - 1 if t_index is None else int(t_index)
+    n_te = torch.empty(n_r, dtype=torch.float64, device=dev) if want_n else None
+    loss = torch.empty(1, dtype=torch.float64, device=dev) if w is not None else None
+    dV = dU = dJ = None
+    if grads:
+        if w is None:
+            raise ValueError("gradients need loss weights w")
+        dV = torch.empty(n_r, dtype=torch.float64, device=dev)
+        dU = torch.empty(prob.n_real, dtype=torch.float64, device=dev)
+        dJ = torch.empty(prob.n_real, dtype=torch.float64, device=dev)
+    need = adjoint_workspace_bytes(prob, prec)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    st = Stats()
+    rc = lib().dyson_adjoint(ctypes.byref(prob), _ptr(S), _ptr(V if grads else None),
+                             _ptr(U if grads else None), _ptr(J), _ptr(w), t_index, int(prec),
+                             float(tol), int(max_iter), _ptr(n_te), _ptr(loss), _ptr(dV), _ptr(dU),
+                             _ptr(dJ), _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
+                             _stream(stream))
+    _check(rc, st.as_dict())
+    return {"n_te": n_te, "loss": loss, "dV": dV, "dU": dU, "dJ": dJ, "stats": st.as_dict()}
+
+
+def _density_fn():
+    import torch
+
+    class DysonDensity(torch.autograd.Function):
+        """n_l(t_e) for every site as a differentiable function of the trap
+        potential V, the interaction U(t) and the hopping J(t).  The backward
+        pass is the hand-written adjoint Dyson solve (dyson_adjoint), which
+        recomputes the forward columns instead of storing iterates."""
+
+        @staticmethod
+        def forward(ctx, V, U, J, prob, t_index, prec, tol):
+            S = sigma_build(prob, V, U)
+            out = dyson_adjoint(prob, S, V, U, J, w=None, t_index=t_index, prec=prec, tol=tol,
+                                grads=False)
+            ctx.save_for_backward(V, U, J)
+            ctx.cfg = (prob, t_index, prec, tol)
+            return out["n_te"]
+
+        @staticmethod
+        def backward(ctx, grad_n):
+            V, U, J = ctx.saved_tensors
+            prob, t_index, prec, tol = ctx.cfg
+            S = sigma_build(prob, V, U)
+            out = dyson_adjoint(prob, S, V, U, J, w=grad_n.contiguous().to(torch.float64),
+                                t_index=t_index, prec=prec, tol=tol, grads=True, want_n=False)
+            return out["dV"], out["dU"], out["dJ"], None, None, None, None
+
+    return DysonDensity
+
+
+_DENSITY_FN = None
+
+
+def density_at(prob: Problem, V, U, J, t_index=None, prec=PREC_FP64, tol=1e-12):
+    """Differentiable n_l(t_e) (torch tensors V, U, J on the device)."""
+    global _DENSITY_FN
+    if _DENSITY_FN is None:
+        _DENSITY_FN = _density_fn()
+    t_index = prob.n_real - 1 if t_index is None else int(t_index)
+    return _DENSITY_FN.apply(V, U, J, prob, t_index, prec, tol)

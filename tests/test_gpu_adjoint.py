@@ -1,0 +1,122 @@
+"""GPU parity of the adjoint: dyson_adjoint (through the C-ABI) against the
+oracle's dense gradients of L = sum_l w_l n_l(t_end), against central finite
+differences of the library's own densities, and through torch.autograd."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1309_5994_amd import workloads as W
+from helpers import gpu_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _B():
+    from paper_1309_5994_amd import scdyson as B
+    return B
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _modulated(wl, amp_u=0.2, amp_j=0.3):
+    t = wl.t_min + wl.dt * np.arange(wl.n_real)
+    U = 1.0 + amp_u * np.sin(2.0 * t)
+    J = wl.J[0] * (1.0 - amp_j * np.sin(2.0 * t))
+    return W.Workload(**{**wl.__dict__, "U": U, "J": J})
+
+
+CASES = [
+    (W.config(1), False),
+    (_modulated(W.custom(3, 4, 6, 5, J0=0.1, beta=3.0, seed=31)), False),
+    (_modulated(W.custom(4, 3, 5, 4, J0=0.12, beta=2.5, periodic=True, seed=32)), True),
+]
+
+
+@pytest.mark.parametrize("wl,periodic", CASES, ids=["cfg1", "mod3x4", "mod_periodic4x3"])
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_adjoint_matches_dense_oracle(wl, periodic, prec, device):
+    import torch
+    B = _B()
+    prob, V, U, J = gpu_inputs(wl, device)
+    w_np = W.loss_weights(wl.n_r)
+    w = torch.tensor(w_np, dtype=torch.float64, device=device)
+    S = B.sigma_build(prob, V, U)
+    out = B.dyson_adjoint(prob, S, V, U, J, w=w, prec=prec, tol=1e-13)
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.t_min)
+    L, dV, dU, dJ = O.loss_and_grad_dense(wl.V, wl.U, wl.J, wl.mu, wl.Lx, wl.Ly, wl.periodic, c,
+                                          w_np)
+    tol = 1e-11 if prec == 0 else 1e-8
+    assert abs(float(_np(out["loss"])[0]) - L) <= tol * max(1.0, abs(L))
+    for got, ref in ((out["dV"], dV), (out["dU"], dU), (out["dJ"], dJ)):
+        got = _np(got)
+        assert np.abs(got - ref).max() <= tol * max(1.0, np.abs(ref).max()), (got, ref)
+
+
+def test_adjoint_forward_only_densities_match_full_solve(device):
+    B = _B()
+    wl = W.config(1)
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = B.sigma_build(prob, V, U)
+    only = B.dyson_adjoint(prob, S, V, U, J, grads=False, tol=1e-13)
+    full = B.dyson_iterate(prob, S, J, list(range(wl.n_r)), tol=1e-13)
+    n_full, _ = B.local_observables(prob, full["G_loc"], full["G_nn"], J)
+    assert np.abs(_np(only["n_te"]) - _np(n_full)[:, -1]).max() <= 1e-13
+
+
+def test_config4_gradients_against_finite_differences(device):
+    """12x12 trap, N_t = 112: dL/dV_i and dL/dJ(t) against central differences of
+    the library's own loss (h = 1e-5; FD truncation ~1e-10)."""
+    import torch
+    B = _B()
+    wl = W.config(4)
+    prob, V, U, J = gpu_inputs(wl, device)
+    w = torch.tensor(W.loss_weights(wl.n_r), dtype=torch.float64, device=device)
+    S = B.sigma_build(prob, V, U)
+    ws = torch.empty(B.adjoint_workspace_bytes(prob), dtype=torch.uint8, device=device)
+    g = B.dyson_adjoint(prob, S, V, U, J, w=w, tol=1e-13, ws=ws)
+
+    def loss(Vx, Ux, Jx):
+        Sx = B.sigma_build(prob, Vx, Ux)
+        r = B.dyson_adjoint(prob, Sx, Vx, Ux, Jx, w=w, grads=False, want_n=False, tol=1e-14,
+                            ws=ws)
+        return float(_np(r["loss"])[0])
+
+    h = 1e-5
+    rng = np.random.default_rng(4)
+    for i in [int(x) for x in rng.choice(wl.n_r, 6, replace=False)] + [wl.n_r // 2 + 6]:
+        e = torch.zeros_like(V)
+        e[i] = h
+        fd = (loss(V + e, U, J) - loss(V - e, U, J)) / (2 * h)
+        assert abs(fd - float(g["dV"][i])) <= 1e-7 * max(1.0, abs(fd)), i
+    for k in [0, 1, 17, wl.n_real - 2, wl.n_real - 1]:
+        e = torch.zeros_like(J)
+        e[k] = h
+        fd = (loss(V, U, J + e) - loss(V, U, J - e)) / (2 * h)
+        assert abs(fd - float(g["dJ"][k])) <= 1e-7 * max(1.0, abs(fd)), k
+    for k in [0, 5, wl.n_real - 1]:
+        e = torch.zeros_like(U)
+        e[k] = h
+        fd = (loss(V, U + e, J) - loss(V, U - e, J)) / (2 * h)
+        assert abs(fd - float(g["dU"][k])) <= 1e-7 * max(1.0, abs(fd)), k
+
+
+def test_autograd_function(device):
+    import torch
+    B = _B()
+    wl = _modulated(W.custom(3, 3, 5, 4, J0=0.1, beta=2.0, seed=40))
+    prob, V, U, J = gpu_inputs(wl, device)
+    V.requires_grad_(True)
+    U.requires_grad_(True)
+    J.requires_grad_(True)
+    n = B.density_at(prob, V, U, J, tol=1e-13)
+    w = torch.tensor(W.loss_weights(wl.n_r), dtype=torch.float64, device=device)
+    (n * w).sum().backward()
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.t_min)
+    L, dV, dU, dJ = O.loss_and_grad_dense(wl.V, wl.U, wl.J, wl.mu, wl.Lx, wl.Ly, False, c,
+                                          W.loss_weights(wl.n_r))
+    assert abs(float((n * w).sum()) - L) < 1e-12
+    assert np.abs(_np(V.grad) - dV).max() < 1e-11
+    assert np.abs(_np(U.grad) - dU).max() < 1e-11
+    assert np.abs(_np(J.grad) - dJ).max() < 1e-11

@@ -74,45 +74,45 @@ int check_problem(const scd_problem* p, int max_nt, Geom* g) {
 struct Layout {
     int ldx, ntn, nwg;
     size_t off_st, off_st32, off_x0, off_x1, off_r32, off_d0, off_d1, off_partial, off_slot,
-        off_src, total;
+        off_src, off_order, total;
 };
 
-// Workspace: St (FP64 operand), two FP64 iterates (FP64 path) or one FP64
-// iterate + St32 + residual and two corrections in complex64 (FP32 path).
+bool lattice_bipartite(const Geom& g) { return !g.periodic || (g.Lx % 2 == 0 && g.Ly % 2 == 0); }
+
+// Workspace: St (FP64 operand) and one FP64 iterate, updated in place by
+// red-black sweeps; FP32 path: + St32, the complex64 residual and one
+// correction.  A lattice that is not bipartite (periodic with an odd extent)
+// sweeps Jacobi-style and needs a second FP64 iterate (second correction).
 Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
     Layout L;
     const int bs = block_sites < n_src ? block_sites : n_src;
+    const bool rb = lattice_bipartite(g);
     L.ldx = ((bs * g.n_t + kColsPerWG - 1) / kColsPerWG) * kColsPerWG;
     L.ntn = L.ldx / kColsPerWG;
     L.nwg = g.n_r * L.ntn;
-    const size_t it64 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
-    const size_t it32 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(float2));
+    const size_t it64 = (size_t)g.n_r * g.mp * L.ldx * sizeof(double2);
+    const size_t it32 = (size_t)g.n_r * g.mp * L.ldx * sizeof(float2);
     size_t off = 0;
-    L.off_st = off;
-    off += align256((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
-    L.off_x0 = off;
-    off += it64;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.off_st = take((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
+    L.off_x0 = take(it64);
+    L.off_x1 = L.off_st32 = L.off_r32 = L.off_d0 = L.off_d1 = 0;
     if (prec == SCD_PREC_FP64) {
-        L.off_x1 = off;
-        off += it64;
-        L.off_st32 = L.off_r32 = L.off_d0 = L.off_d1 = 0;
+        if (!rb) L.off_x1 = take(it64);
     } else {
-        L.off_x1 = 0;
-        L.off_st32 = off;
-        off += align256((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
-        L.off_r32 = off;
-        off += it32;
-        L.off_d0 = off;
-        off += it32;
-        L.off_d1 = off;
-        off += it32;
+        L.off_st32 = take((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
+        L.off_r32 = take(it32);
+        L.off_d0 = take(it32);
+        if (!rb) L.off_d1 = take(it32);
     }
-    L.off_partial = off;
-    off += align256((size_t)L.nwg * 3 * sizeof(double));
-    L.off_slot = off;
-    off += align256(4 * sizeof(unsigned long long));
-    L.off_src = off;
-    off += align256((size_t)n_src * sizeof(int32_t));
+    L.off_partial = take((size_t)L.nwg * 3 * sizeof(double));
+    L.off_slot = take(4 * sizeof(unsigned long long));
+    L.off_src = take((size_t)n_src * sizeof(int32_t));
+    L.off_order = take((size_t)g.n_r * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -158,6 +158,18 @@ struct BlockResult {
     double err = 0.0, rho = 0.0;
 };
 
+// Sites of the two colours of a bipartite lattice: (x + y) even, then odd.
+std::vector<int32_t> colour_order(const Geom& g, int* n_even) {
+    std::vector<int32_t> order;
+    order.reserve(g.n_r);
+    for (int c = 0; c < 2; ++c) {
+        for (int i = 0; i < g.n_r; ++i)
+            if (((i / g.Ly) + (i % g.Ly)) % 2 == c) order.push_back(i);
+        if (c == 0) *n_even = (int)order.size();
+    }
+    return order;
+}
+
 // Host side of the sweep loops of one column block.
 struct Solver {
     Geom g;
@@ -169,29 +181,37 @@ struct Solver {
     double* partial;
     unsigned long long* slot;
     int nwg;
+    const int* colour_sites[2] = {nullptr, nullptr};   // device site lists (red-black)
+    int n_colour[2] = {0, 0};
     EventPair ev;
-    std::vector<double> within;   // (target, source) pairs within lattice distance d, cumulative
+    std::vector<double> within[3];   // (target, source) pairs within distance d, cumulative:
+                                     // [0] all targets, [1] even-colour, [2] odd-colour targets
 
     void pair_counts(const int32_t* src_host, int bs) {
-        within.assign(g.Lx + g.Ly + 1, 0.0);
+        for (auto& w : within) w.assign(g.Lx + g.Ly + 1, 0.0);
         for (int s = 0; s < bs; ++s) {
             const int j = src_host[s];
             const int xj = j / g.Ly, yj = j % g.Ly;
             for (int i = 0; i < g.n_r; ++i) {
-                int dx = std::abs(i / g.Ly - xj), dy = std::abs(i % g.Ly - yj);
+                const int xi = i / g.Ly, yi = i % g.Ly;
+                int dx = std::abs(xi - xj), dy = std::abs(yi - yj);
                 if (g.periodic) {
                     dx = std::min(dx, g.Lx - dx);
                     dy = std::min(dy, g.Ly - dy);
                 }
-                within[dx + dy] += 1.0;
+                within[0][dx + dy] += 1.0;
+                within[1 + (xi + yi) % 2][dx + dy] += 1.0;
             }
         }
-        for (size_t d = 1; d < within.size(); ++d) within[d] += within[d - 1];
+        for (auto& w : within)
+            for (size_t d = 1; d < w.size(); ++d) w[d] += w[d - 1];
     }
-    // Algorithmic flops of a sweep whose output reaches lattice distance `radius`.
-    double sweep_flops(int radius, int cols_per_src) const {
-        const size_t last = within.size() - 1;
-        const double pairs = within[(size_t)radius < last ? (size_t)radius : last];
+    // Algorithmic flops of a launch whose output reaches lattice distance
+    // `radius` on the targets of `which` (0 all, 1 even, 2 odd colour).
+    double sweep_flops(int radius, int cols_per_src, int which = 0) const {
+        const std::vector<double>& w = within[which];
+        const size_t last = w.size() - 1;
+        const double pairs = w[(size_t)radius < last ? (size_t)radius : last];
         return 8.0 * g.n_t * (double)g.n_t * (double)cols_per_src * pairs;
     }
     // Fold the per-workgroup partials of the last sweep; returns SCD_OK or SCD_EHIP.
@@ -210,28 +230,66 @@ struct Solver {
         *seconds = 1e-3 * ms;
         return SCD_OK;
     }
+    bool red_black() const { return colour_sites[0] != nullptr; }
 
-    // Plain FP64 Jacobi sweeps X <- X0 + St^T N(X) until the relative increment
-    // and its contraction-corrected error estimate are below tol.
+    // One sweep X <- X0 + St^T N(X): red-black in place (Xn unused) or Jacobi
+    // into Xn.  `half` counts the launches already applied (light-cone radius).
+    int sweep_fp64(SweepArgs a, const int* src_blk, double2* X, double2* Xn, int cps, int* half,
+                   double* secs_out) {
+        double secs_total = 0.0;
+        const bool cone = a.lc_sweep >= 0;
+        if (red_black()) {
+            int off = 0;
+            for (int c = 0; c < 2; ++c) {
+                a.sites = colour_sites[c];
+                a.n_sites = n_colour[c];
+                a.part_off = off;
+                a.lc_sweep = cone ? *half : -1;
+                SCD_HIP(hipEventRecord(ev.a, st), "event record");
+                SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, X, X, partial, st), "sweep launch");
+                SCD_HIP(hipEventRecord(ev.b, st), "event record");
+                SCD_HIP(hipEventSynchronize(ev.b), "event sync");
+                double secs;
+                if (elapsed(&secs)) return SCD_EHIP;
+                secs_total += secs;
+                stats->sweep_launches++;
+                stats->gemm_flops += sweep_flops(cone ? *half + 1 : 1 << 20, cps, 1 + c);
+                off += n_colour[c] * a.ntn;
+                ++*half;
+            }
+        } else {
+            a.sites = nullptr;
+            a.n_sites = g.n_r;
+            a.part_off = 0;
+            a.lc_sweep = cone ? *half : -1;
+            SCD_HIP(hipEventRecord(ev.a, st), "event record");
+            SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, X, Xn, partial, st), "sweep launch");
+            SCD_HIP(hipEventRecord(ev.b, st), "event record");
+            SCD_HIP(hipEventSynchronize(ev.b), "event sync");
+            if (elapsed(&secs_total)) return SCD_EHIP;
+            stats->sweep_launches++;
+            stats->gemm_flops += sweep_flops(cone ? *half + 1 : 1 << 20, cps, 0);
+            ++*half;
+        }
+        *secs_out = secs_total;
+        return SCD_OK;
+    }
+
+    // FP64 sweeps until the relative increment and its contraction-corrected
+    // error estimate are below tol.
     int solve_fp64(SweepArgs a, const int* src_blk, double2* X, double2* Xn, double tol,
                    int max_iter, BlockResult* res) {
         const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
         double e_prev = 0.0, d_prev = 0.0, rho = 0.0, e_n = 0.0;
-        int grow = 0, n = 0, code = SCD_ENOTCONV;
+        int grow = 0, n = 0, code = SCD_ENOTCONV, half = 0;
         double2* cur = X;
         double2* nxt = Xn;
         for (n = 1; n <= max_iter; ++n) {
-            a.lc_sweep = a.lc_sweep < 0 ? -1 : n - 1;
-            SCD_HIP(hipEventRecord(ev.a, st), "event record");
-            SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, cur, nxt, partial, st), "sweep launch");
-            SCD_HIP(hipEventRecord(ev.b, st), "event record");
             double r[3], secs;
-            if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
-            std::swap(cur, nxt);
+            if (sweep_fp64(a, src_blk, cur, nxt, cps, &half, &secs) || reduce(r)) return SCD_EHIP;
+            if (!red_black()) std::swap(cur, nxt);
             stats->fp64_sweeps++;
-            stats->sweep_launches++;
             stats->sweep_kernel_seconds += secs;
-            stats->gemm_flops += sweep_flops(a.lc_sweep < 0 ? 1 << 20 : n, cps);
             if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
                 code = fail(SCD_ENAN, "NaN or Inf in the iterate at sweep %d", n);
                 break;
@@ -266,9 +324,11 @@ struct Solver {
     }
 
     // Iterative refinement: FP64 residual R = X0 + St^T N(X) - X (complex64
-    // output), FP32-MFMA correction sweeps D <- R + St^T N(D) to a relative
-    // increment of 1e-6 (or stagnation), then X += D in FP64.  Stops when the
-    // relative FP64 residual, divided by (1 - rho), is below tol.
+    // output), FP32-MFMA correction sweeps D <- R + St^T N(D) (red-black in
+    // place, or Jacobi between D0 and D1) to the relative increment the outer
+    // target needs (at most 0.1, at least the FP32 floor 1e-6, or until
+    // stagnation), then X += D in FP64.  Stops when the relative FP64
+    // residual, divided by (1 - rho), is below tol.
     int solve_mixed(SweepArgs a, const int* src_blk, double2* X, void* R32, void* D0, void* D1,
                     double tol, int max_iter, BlockResult* res) {
         const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
@@ -276,14 +336,16 @@ struct Solver {
         const size_t bytes32 = n_elem * sizeof(float2);
         SCD_HIP(hipMemsetAsync(R32, 0, bytes32, st), "clear");
         SCD_HIP(hipMemsetAsync(D0, 0, bytes32, st), "clear");
-        SCD_HIP(hipMemsetAsync(D1, 0, bytes32, st), "clear");
+        if (D1) SCD_HIP(hipMemsetAsync(D1, 0, bytes32, st), "clear");
         const bool cone = a.lc_sweep >= 0;
         int radius_x = 0;           // lattice distance the iterate reaches
         double rho = 0.0, e_r = 0.0, d_prev = 0.0;
         int outer = 0, code = SCD_ENOTCONV, grow = 0;
         const int max_inner = 1000;
-        const double inner_tol = 1e-6;
         for (outer = 1; outer <= max_iter; ++outer) {
+            a.sites = nullptr;
+            a.n_sites = g.n_r;
+            a.part_off = 0;
             a.lc_sweep = cone ? radius_x : -1;
             SCD_HIP(hipEventRecord(ev.a, st), "event record");
             SCD_HIP(launch_residual_f64(g, a, St, S, src_blk, X, R32, partial, st),
@@ -313,25 +375,45 @@ struct Solver {
             }
             d_prev = r[0];
             if (outer == max_iter) break;
-            // Correction sweeps from D_0 = R.
+            // Correction sweeps from D_0 = R, solved only as accurately as the
+            // outer target needs: the corrected X is off by about
+            // eta |R| / (1 - rho) for a relative correction accuracy eta.
+            const double rho_g = (rho > 0.0 && rho < 1.0) ? rho : 0.5;
+            const double inner_tol =
+                std::min(0.1, std::max(1e-6, 0.3 * tol * (1.0 - rho_g) / e_r));
             const int radius_r = radius_x + 1;
             SCD_HIP(launch_copy_f32(R32, D0, n_elem, st), "copy launch");
             void* dc = D0;
             void* dn = D1;
             double e_prev = 0.0;
-            int j = 0, stall = 0;
+            int j = 0, stall = 0, half = radius_r;
             for (j = 1; j <= max_inner; ++j) {
-                a.lc_sweep = cone ? radius_r + j - 1 : -1;
-                SCD_HIP(hipEventRecord(ev.a, st), "event record");
-                SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, dc, dn, partial, st),
-                        "correct launch");
-                SCD_HIP(hipEventRecord(ev.b, st), "event record");
-                if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
-                std::swap(dc, dn);
+                double secs_sum = 0.0;
+                const int launches = red_black() ? 2 : 1;
+                int off = 0;
+                for (int c = 0; c < launches; ++c) {
+                    a.sites = red_black() ? colour_sites[c] : nullptr;
+                    a.n_sites = red_black() ? n_colour[c] : g.n_r;
+                    a.part_off = off;
+                    a.lc_sweep = cone ? half : -1;
+                    SCD_HIP(hipEventRecord(ev.a, st), "event record");
+                    SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, dc,
+                                               red_black() ? dc : dn, partial, st),
+                            "correct launch");
+                    SCD_HIP(hipEventRecord(ev.b, st), "event record");
+                    SCD_HIP(hipEventSynchronize(ev.b), "event sync");
+                    if (elapsed(&secs)) return SCD_EHIP;
+                    secs_sum += secs;
+                    stats->lowp_launches++;
+                    stats->gemm_flops +=
+                        sweep_flops(cone ? half + 1 : 1 << 20, cps, red_black() ? 1 + c : 0);
+                    off += a.n_sites * a.ntn;
+                    ++half;
+                }
+                if (reduce(r)) return SCD_EHIP;
+                if (!red_black()) std::swap(dc, dn);
                 stats->lowp_sweeps++;
-                stats->lowp_launches++;
-                stats->lowp_kernel_seconds += secs;
-                stats->gemm_flops += sweep_flops(cone ? radius_r + j : 1 << 20, cps);
+                stats->lowp_kernel_seconds += secs_sum;
                 if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
                     code = fail(SCD_ENAN, "NaN or Inf in an FP32 correction sweep");
                     break;
@@ -344,7 +426,7 @@ struct Solver {
             }
             if (code == SCD_ENAN) break;
             SCD_HIP(launch_axpy_f32_to_f64(X, dc, n_elem, st), "axpy launch");
-            radius_x = radius_r + (j > max_inner ? max_inner : j);
+            radius_x = half;
         }
         res->X = X;
         res->sweeps = outer > max_iter ? max_iter : outer;
@@ -452,6 +534,19 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
 
     SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
             "copy src");
+    std::vector<int32_t> order;
+    if (lattice_bipartite(g)) {
+        int n_even = 0;
+        order = colour_order(g, &n_even);
+        int* order_dev = (int*)(base + L.off_order);
+        SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st),
+                "copy colour order");
+        sv.colour_sites[0] = order_dev;
+        sv.colour_sites[1] = order_dev + n_even;
+        sv.n_colour[0] = n_even;
+        sv.n_colour[1] = g.n_r - n_even;
+    }
     SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, 0, st), "scale_transpose launch");
     if (sv.St32)
         SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
@@ -477,19 +572,21 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         a.group = site_group(g);
         a.x0_kind = X0_BLOCK;
         a.x0_fixed = 0;
+        a.sites = nullptr;
+        a.n_sites = g.n_r;
+        a.part_off = 0;
         sv.pair_counts(src + blk_start, bs);
         double2* X = (double2*)(base + L.off_x0);
-        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, X0_BLOCK, 0, X,
-                                  prec == SCD_PREC_FP64 ? (double2*)(base + L.off_x1) : nullptr,
-                                  st),
+        double2* Xn = L.off_x1 ? (double2*)(base + L.off_x1) : nullptr;
+        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, X0_BLOCK, 0, X, Xn, st),
                 "init_block launch");
         BlockResult res;
         int code;
         if (prec == SCD_PREC_FP64) {
-            code = sv.solve_fp64(a, src_blk, X, (double2*)(base + L.off_x1), tol, max_iter, &res);
+            code = sv.solve_fp64(a, src_blk, X, Xn, tol, max_iter, &res);
         } else {
             code = sv.solve_mixed(a, src_blk, X, base + L.off_r32, base + L.off_d0,
-                                  base + L.off_d1, tol, max_iter, &res);
+                                  L.off_d1 ? base + L.off_d1 : nullptr, tol, max_iter, &res);
         }
         if (code == SCD_EHIP) return finish(code);
         if (code == SCD_ENOTCONV)
@@ -522,7 +619,8 @@ namespace {
 struct AdjLayout {
     int ldx, ntn, nwg;
     size_t off_st, off_stt, off_st32, off_stt32, off_xg, off_xh, off_x1, off_r32, off_d0, off_d1,
-        off_lam, off_rsum, off_csum, off_bz, off_djc, off_partial, off_slot, off_src, total;
+        off_lam, off_rsum, off_csum, off_bz, off_djc, off_partial, off_slot, off_src, off_order,
+        total;
 };
 
 AdjLayout adj_layout(const Geom& g, int prec) {
@@ -544,15 +642,16 @@ AdjLayout adj_layout(const Geom& g, int prec) {
     L.off_stt = take(op64);
     L.off_xg = take(it64);
     L.off_xh = take(it64);
+    const bool rb = lattice_bipartite(g);
     L.off_st32 = L.off_stt32 = L.off_x1 = L.off_r32 = L.off_d0 = L.off_d1 = 0;
     if (prec == SCD_PREC_FP64) {
-        L.off_x1 = take(it64);
+        if (!rb) L.off_x1 = take(it64);
     } else {
         L.off_st32 = take(op32);
         L.off_stt32 = take(op32);
         L.off_r32 = take(it32);
         L.off_d0 = take(it32);
-        L.off_d1 = take(it32);
+        if (!rb) L.off_d1 = take(it32);
     }
     L.off_lam = take((size_t)g.n_r * g.n_t * g.n_t * sizeof(double2));
     L.off_rsum = take((size_t)g.n_r * g.n_t * sizeof(double2));
@@ -562,6 +661,7 @@ AdjLayout adj_layout(const Geom& g, int prec) {
     L.off_partial = take((size_t)L.nwg * 3 * sizeof(double));
     L.off_slot = take(4 * sizeof(unsigned long long));
     L.off_src = take((size_t)g.n_r * sizeof(int32_t));
+    L.off_order = take((size_t)g.n_r * sizeof(int32_t));
     L.total = off;
     return L;
 }
@@ -644,6 +744,19 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
     sv.nwg = L.nwg;
     SCD_HIP(sv.ev.create(), "event create");
     sv.pair_counts(ident.data(), g.n_r);
+    std::vector<int32_t> order;
+    if (lattice_bipartite(g)) {
+        int n_even = 0;
+        order = colour_order(g, &n_even);
+        int* order_dev = (int*)(base + L.off_order);
+        SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st),
+                "copy colour order");
+        sv.colour_sites[0] = order_dev;
+        sv.colour_sites[1] = order_dev + n_even;
+        sv.n_colour[0] = n_even;
+        sv.n_colour[1] = g.n_r - n_even;
+    }
 
     const int e = t_index, be = 2 * g.n_real - 1 - t_index;
     double worst_err = 0.0, worst_rho = 0.0;
@@ -662,21 +775,24 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
         a.group = site_group(g);
         a.x0_kind = pass == 0 ? X0_COL : X0_COL_T;
         a.x0_fixed = pass == 0 ? be : e;
+        a.sites = nullptr;
+        a.n_sites = g.n_r;
+        a.part_off = 0;
         sv.St = pass == 0 ? St : StT;
         sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + (pass == 0 ? L.off_st32 : L.off_stt32))
                                         : nullptr;
         double2* X = (double2*)(base + (pass == 0 ? L.off_xg : L.off_xh));
+        double2* Xn = L.off_x1 ? (double2*)(base + L.off_x1) : nullptr;
         SCD_HIP(launch_init_block(g, (const double2*)S, src_dev, g.n_r, L.ldx, a.x0_kind,
-                                  a.x0_fixed, X,
-                                  prec == SCD_PREC_FP64 ? (double2*)(base + L.off_x1) : nullptr, st),
+                                  a.x0_fixed, X, Xn, st),
                 "init launch");
         BlockResult res;
         int code;
         if (prec == SCD_PREC_FP64) {
-            code = sv.solve_fp64(a, src_dev, X, (double2*)(base + L.off_x1), tol, max_iter, &res);
+            code = sv.solve_fp64(a, src_dev, X, Xn, tol, max_iter, &res);
         } else {
             code = sv.solve_mixed(a, src_dev, X, base + L.off_r32, base + L.off_d0,
-                                  base + L.off_d1, tol, max_iter, &res);
+                                  L.off_d1 ? base + L.off_d1 : nullptr, tol, max_iter, &res);
         }
         if (code == SCD_ENOTCONV)
             fail(SCD_ENOTCONV, "%s solve not converged after %d sweeps (e=%g)",

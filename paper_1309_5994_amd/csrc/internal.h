@@ -43,6 +43,10 @@ struct SweepArgs {
     int group;      // tile order: groups of `group` consecutive sites, column tile major inside
     int x0_kind;    // X0_BLOCK, X0_COL or X0_COL_T (what X0 holds on a source's own site)
     int x0_fixed;   // the fixed contour index of X0_COL / X0_COL_T
+    const int* sites;  // sites updated by this launch (one colour of a red-black
+                       // sweep), or nullptr for all sites in index order
+    int n_sites;    // number of updated sites
+    int part_off;   // offset (in workgroups) of this launch's convergence partials
 };
 
 // X0 of a column block (the preconditioned unit-vector bundle):

@@ -24,6 +24,12 @@
 //    whose sources are all farther than n+1 from site i is skipped (its output
 //    stays zero).
 //
+// Red-black ordering: on a bipartite lattice the neighbours of one colour are
+// all of the other colour, so a launch over one colour can update X in place
+// (each workgroup reads its own tile before overwriting it and only
+// neighbour tiles of the other colour); two such launches form a Gauss-Seidel
+// sweep, whose contraction rate is the square of the Jacobi sweep's.
+//
 // Modes:
 //  * SOLVE     (FP64): X0 from S; writes Y; partials max|Y - X|, max|Y|.
 //  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64; partials
@@ -70,8 +76,8 @@ struct EngF32 {
 template <class E, int MT, int MODE>
 __global__ __launch_bounds__(kThreads)
 void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restrict__ S,
-                  const int* __restrict__ src_blk, const typename E::cplx* __restrict__ X,
-                  void* __restrict__ out, const fvec2* __restrict__ R,
+                  const int* __restrict__ src_blk, const typename E::cplx* X, void* out,
+                  const fvec2* __restrict__ R,
                   double* __restrict__ partial, SweepArgs g) {
     typedef typename E::real real;
     typedef typename E::cplx cplx;
@@ -102,7 +108,9 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
 
     const int tile = xcd_remap(blockIdx.x, gridDim.x);
     int i, ct;
-    tile_site_col(tile, g.ntn, g.n_r, g.group, &i, &ct);
+    tile_site_col(tile, g.ntn, g.n_sites, g.group, &i, &ct);
+    if (g.sites) i = g.sites[i];
+    double* part = partial + 3 * (size_t)g.part_off;
     const int n0 = ct * NW;
     const int ldx = g.ldx;
     const int cols_per_src = (g.x0_kind == X0_BLOCK) ? g.n_t : 1;
@@ -129,7 +137,7 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
             dmin = dmin < dx + dy ? dmin : dx + dy;
         }
         if (s_lo >= g.bs || dmin > g.lc_sweep + 1) {
-            if (tid < 3) partial[3 * blockIdx.x + tid] = 0.0;
+            if (tid < 3) part[3 * blockIdx.x + tid] = 0.0;
             return;
         }
     }
@@ -276,7 +284,7 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     if (tid < 3) {
         double m = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) m = fmax(m, red[w][tid]);
-        partial[3 * blockIdx.x + tid] = m;
+        part[3 * blockIdx.x + tid] = m;
     }
 }
 
@@ -284,7 +292,7 @@ template <class E, int MODE>
 hipError_t launch_mode(const Geom& g, const SweepArgs& a, const void* St, const double2* S,
                        const int* src_blk, const void* X, void* out, const void* R,
                        double* partial, hipStream_t st) {
-    dim3 grid(g.n_r * a.ntn);
+    dim3 grid(a.n_sites * a.ntn);
     typedef typename E::cplx cplx;
     const cplx* St_ = reinterpret_cast<const cplx*>(St);
     const cplx* X_ = reinterpret_cast<const cplx*>(X);

@@ -22,6 +22,26 @@ sys.path.insert(0, ROOT)
 from paper_1309_5994_amd import workloads as W          # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (MFMA = vector)
+SWEEP_SOURCE = os.path.join(ROOT, "paper_1309_5994_amd", "csrc", "sweep.hip")
+PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_fp64_trap16x16_nt144.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the FP64 sweep kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source (else None)."""
+    import hashlib
+    try:
+        sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()[:16]
+        for line in open(PROFILE):
+            if line.startswith("traffic-record:"):
+                fields = dict(kv.split("=", 1) for kv in line.split()[1:])
+                if fields.get("source_sha256_16") != sha:
+                    return None
+                return float(fields["fetch_bytes_per_launch"]) + float(
+                    fields["write_bytes_per_launch"])
+    except OSError:
+        return None
+    return None
 
 
 def parse():
@@ -32,6 +52,8 @@ def parse():
     ap.add_argument("--workload", type=int, default=2, help="named workload 1..5")
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
+    ap.add_argument("--quick", action="store_true",
+                    help="skip the FP64-vs-mixed time-to-solution legs (profiling runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -133,7 +155,7 @@ def main():
         "rho_est": stats[-1]["rho_est"],
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                     "traffic": None, "kernel": "sweep_f64_kernel",
+                     "traffic": measured_traffic(), "kernel": "sweep_kernel<EngF64>",
                      "avg_launch_ms": round(1e3 * kern_s / max(launches, 1), 4),
                      "flops_per_launch": flops / max(launches, 1)},
     }
@@ -141,10 +163,11 @@ def main():
     # errors are measured against the FP64 run at 1e-12 above.
     n_ref = n.clone()
     tts = {}
-    for label, prec, tol in (("fp64_tol1e-12", B.PREC_FP64, args.tol),
+    legs = () if args.quick else (("fp64_tol1e-12", B.PREC_FP64, args.tol),
                              ("fp64_tol1e-9", B.PREC_FP64, 1e-9),
                              ("mixed_fp32_tol1e-9", B.PREC_FP32, 1e-9),
-                             ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12)):
+                                  ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12))
+    for label, prec, tol in legs:
         ws_p = ws if prec == B.PREC_FP64 else torch.empty(
             B.workspace_bytes(prob, len(src), block, prec), dtype=torch.uint8, device=dev)
         for rep in range(2):          # first repetition warms up
@@ -164,7 +187,8 @@ def main():
                       "fp64_kernel_ms": round(1e3 * st_p["sweep_kernel_seconds"], 2),
                       "fp32_kernel_ms": round(1e3 * st_p["lowp_kernel_seconds"], 2),
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
-    rec["time_to_solution"] = tts
+    if tts:
+        rec["time_to_solution"] = tts
     if not args.no_cpu:
         per_source = stats[-1]["gemm_flops"] / len(src)
         rec["cpu_baseline"] = cpu_baseline(wl, per_source)

@@ -117,20 +117,6 @@ Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
     return L;
 }
 
-// Two timing events, destroyed on every exit path.
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    hipError_t create() {
-        hipError_t e = hipEventCreate(&a);
-        if (e == hipSuccess) e = hipEventCreate(&b);
-        return e;
-    }
-    ~EventPair() {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
-
 // Sites per tile-order group of the sweep kernel (see tile_site_col):
 // SCD_SITE_GROUP overrides; the default keeps a group's site operands
 // (mp^2 complex each) within about 2 MB of one XCD's L2.
@@ -159,16 +145,87 @@ struct BlockResult {
 };
 
 // Sites of the two colours of a bipartite lattice: (x + y) even, then odd.
+// Within a colour, sites are listed patch by patch (square patches of
+// `patch` x `patch` lattice sites, x-major inside), so that consecutive
+// workgroups of one launch share the neighbour tiles of the other colour.
+int colour_patch(const Geom& g) {
+    if (const char* env = std::getenv("SCD_PATCH")) {
+        const int v = std::atoi(env);
+        if (v >= 1) return v;
+    }
+    return 1;
+}
+
 std::vector<int32_t> colour_order(const Geom& g, int* n_even) {
+    const int patch = colour_patch(g);
     std::vector<int32_t> order;
     order.reserve(g.n_r);
     for (int c = 0; c < 2; ++c) {
-        for (int i = 0; i < g.n_r; ++i)
-            if (((i / g.Ly) + (i % g.Ly)) % 2 == c) order.push_back(i);
+        for (int bx = 0; bx < g.Lx; bx += patch)
+            for (int by = 0; by < g.Ly; by += patch)
+                for (int x = bx; x < std::min(bx + patch, g.Lx); ++x)
+                    for (int y = by; y < std::min(by + patch, g.Ly); ++y)
+                        if ((x + y) % 2 == c) order.push_back(x * g.Ly + y);
         if (c == 0) *n_even = (int)order.size();
     }
     return order;
 }
+
+// Launch timing without a host sync per launch: events are recorded around
+// each launch and read back at the next convergence check.
+struct LaunchTimer {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    ~LaunchTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t mark(hipStream_t st) {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            hipError_t rc = hipEventCreate(&e);
+            if (rc != hipSuccess) return rc;
+            ev.push_back(e);
+        }
+        return hipEventRecord(ev[used++], st);
+    }
+    // Sum of (end - begin) over the recorded pairs; the stream must be synchronised.
+    hipError_t drain(double* seconds) {
+        double sum = 0.0;
+        for (size_t k = 0; k + 1 < used; k += 2) {
+            float ms = 0.0f;
+            hipError_t rc = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            if (rc != hipSuccess) return rc;
+            sum += 1e-3 * ms;
+        }
+        used = 0;
+        *seconds = sum;
+        return hipSuccess;
+    }
+};
+
+// When to measure convergence: every sweep at first, then at points predicted
+// from the measured contraction rate (see schedule), then every sweep.
+struct CheckPlan {
+    int last_n = 0, next = 1;
+    double last_e = 0.0, rho = 0.0;
+    bool due(int n) const { return n <= 3 || n >= next; }
+    // A measured increment e at sweep n: updates the rate estimate.
+    void record(int n, double e) {
+        if (last_n > 0 && last_e > 0.0 && e > 0.0)
+            rho = std::pow(e / last_e, 1.0 / (double)(n - last_n));
+        last_n = n;
+        last_e = e;
+    }
+    // Next check: after 60 % of the sweeps predicted to bring e below target
+    // (the longer baseline sharpens the rate), every sweep once 2 or fewer remain.
+    void schedule(int n, double e, double target) {
+        int k = 1;
+        if (rho > 0.0 && rho < 1.0 && e > target && target > 0.0)
+            k = (int)std::ceil(std::log(target / e) / std::log(rho));
+        k = std::max(1, std::min(k, 64));
+        next = n + (k <= 2 ? 1 : std::max(1, (int)(0.6 * k)));
+    }
+};
 
 // Host side of the sweep loops of one column block.
 struct Solver {
@@ -183,7 +240,7 @@ struct Solver {
     int nwg;
     const int* colour_sites[2] = {nullptr, nullptr};   // device site lists (red-black)
     int n_colour[2] = {0, 0};
-    EventPair ev;
+    LaunchTimer t64, t32;
     std::vector<double> within[3];   // (target, source) pairs within distance d, cumulative:
                                      // [0] all targets, [1] even-colour, [2] odd-colour targets
 
@@ -214,7 +271,8 @@ struct Solver {
         const double pairs = w[(size_t)radius < last ? (size_t)radius : last];
         return 8.0 * g.n_t * (double)g.n_t * (double)cols_per_src * pairs;
     }
-    // Fold the per-workgroup partials of the last sweep; returns SCD_OK or SCD_EHIP.
+    // Fold the per-workgroup partials of the last sweep and collect the launch
+    // timings; returns SCD_OK or SCD_EHIP.
     int reduce(double out[3]) {
         SCD_HIP(hipMemsetAsync(slot, 0, 4 * sizeof(unsigned long long), st), "slot clear");
         SCD_HIP(launch_reduce_max3(partial, nwg, slot, st), "reduce launch");
@@ -222,104 +280,106 @@ struct Solver {
         SCD_HIP(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st), "slot copy");
         SCD_HIP(hipStreamSynchronize(st), "sweep sync");
         for (int q = 0; q < 3; ++q) out[q] = bits_to_double(h[q]);
-        return SCD_OK;
-    }
-    int elapsed(double* seconds) {
-        float ms = 0.0f;
-        SCD_HIP(hipEventElapsedTime(&ms, ev.a, ev.b), "event time");
-        *seconds = 1e-3 * ms;
+        double s64 = 0.0, s32 = 0.0;
+        SCD_HIP(t64.drain(&s64), "event time");
+        SCD_HIP(t32.drain(&s32), "event time");
+        stats->sweep_kernel_seconds += s64;
+        stats->lowp_kernel_seconds += s32;
         return SCD_OK;
     }
     bool red_black() const { return colour_sites[0] != nullptr; }
 
-    // One sweep X <- X0 + St^T N(X): red-black in place (Xn unused) or Jacobi
-    // into Xn.  `half` counts the launches already applied (light-cone radius).
-    int sweep_fp64(SweepArgs a, const int* src_blk, double2* X, double2* Xn, int cps, int* half,
-                   double* secs_out) {
-        double secs_total = 0.0;
+    // One sweep X <- X0 + St^T N(X) (FP64) or D <- R + St32^T N(D) (FP32
+    // correction): red-black in place, or Jacobi into `nxt`.  `half` counts the
+    // launches already applied (the light-cone radius).
+    int sweep(SweepArgs a, bool fp32, const int* src_blk, void* cur, void* nxt, const void* R32,
+              int cps, int* half) {
         const bool cone = a.lc_sweep >= 0;
-        if (red_black()) {
-            int off = 0;
-            for (int c = 0; c < 2; ++c) {
-                a.sites = colour_sites[c];
-                a.n_sites = n_colour[c];
-                a.part_off = off;
-                a.lc_sweep = cone ? *half : -1;
-                SCD_HIP(hipEventRecord(ev.a, st), "event record");
-                SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, X, X, partial, st), "sweep launch");
-                SCD_HIP(hipEventRecord(ev.b, st), "event record");
-                SCD_HIP(hipEventSynchronize(ev.b), "event sync");
-                double secs;
-                if (elapsed(&secs)) return SCD_EHIP;
-                secs_total += secs;
-                stats->sweep_launches++;
-                stats->gemm_flops += sweep_flops(cone ? *half + 1 : 1 << 20, cps, 1 + c);
-                off += n_colour[c] * a.ntn;
-                ++*half;
-            }
-        } else {
-            a.sites = nullptr;
-            a.n_sites = g.n_r;
-            a.part_off = 0;
+        const int launches = red_black() ? 2 : 1;
+        int off = 0;
+        for (int c = 0; c < launches; ++c) {
+            a.sites = red_black() ? colour_sites[c] : nullptr;
+            a.n_sites = red_black() ? n_colour[c] : g.n_r;
+            a.part_off = off;
             a.lc_sweep = cone ? *half : -1;
-            SCD_HIP(hipEventRecord(ev.a, st), "event record");
-            SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, X, Xn, partial, st), "sweep launch");
-            SCD_HIP(hipEventRecord(ev.b, st), "event record");
-            SCD_HIP(hipEventSynchronize(ev.b), "event sync");
-            if (elapsed(&secs_total)) return SCD_EHIP;
-            stats->sweep_launches++;
-            stats->gemm_flops += sweep_flops(cone ? *half + 1 : 1 << 20, cps, 0);
+            void* out = red_black() ? cur : nxt;
+            LaunchTimer& tm = fp32 ? t32 : t64;
+            SCD_HIP(tm.mark(st), "event record");
+            if (fp32)
+                SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, cur, out, partial, st),
+                        "correct launch");
+            else
+                SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, (const double2*)cur,
+                                         (double2*)out, partial, st),
+                        "sweep launch");
+            SCD_HIP(tm.mark(st), "event record");
+            if (fp32)
+                stats->lowp_launches++;
+            else
+                stats->sweep_launches++;
+            stats->gemm_flops += sweep_flops(cone ? *half + 1 : 1 << 20, cps,
+                                             red_black() ? 1 + c : 0);
+            off += a.n_sites * a.ntn;
             ++*half;
         }
-        *secs_out = secs_total;
         return SCD_OK;
     }
 
-    // FP64 sweeps until the relative increment and its contraction-corrected
-    // error estimate are below tol.
+    // FP64 sweeps until the relative increment e_n and its contraction-corrected
+    // error estimate e_n rho / (1 - rho) are below tol.
     int solve_fp64(SweepArgs a, const int* src_blk, double2* X, double2* Xn, double tol,
                    int max_iter, BlockResult* res) {
         const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
-        double e_prev = 0.0, d_prev = 0.0, rho = 0.0, e_n = 0.0;
+        double e_n = 0.0, d_prev = 0.0;
         int grow = 0, n = 0, code = SCD_ENOTCONV, half = 0;
-        double2* cur = X;
-        double2* nxt = Xn;
+        CheckPlan plan;
+        void* cur = X;
+        void* nxt = Xn;
         for (n = 1; n <= max_iter; ++n) {
-            double r[3], secs;
-            if (sweep_fp64(a, src_blk, cur, nxt, cps, &half, &secs) || reduce(r)) return SCD_EHIP;
+            a.check = (plan.due(n) || n == max_iter) ? 1 : 0;
+            if (sweep(a, false, src_blk, cur, nxt, nullptr, cps, &half)) return SCD_EHIP;
             if (!red_black()) std::swap(cur, nxt);
             stats->fp64_sweeps++;
-            stats->sweep_kernel_seconds += secs;
+            if (!a.check) continue;
+            double r[3];
+            if (reduce(r)) return SCD_EHIP;
             if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
                 code = fail(SCD_ENAN, "NaN or Inf in the iterate at sweep %d", n);
                 break;
             }
             e_n = r[1] > 0.0 ? r[0] / r[1] : 0.0;
-            if (n >= 2 && e_prev > 0.0) rho = e_n / e_prev;
             if (e_n == 0.0) {
                 code = SCD_OK;
                 break;
             }
+            plan.record(n, e_n);
+            const double rho = plan.rho;
             if (e_n <= tol && n >= 2 &&
                 (e_n <= 1e-2 * tol || (rho < 1.0 && e_n * rho / (1.0 - rho) <= tol))) {
                 code = SCD_OK;
                 break;
             }
+            plan.schedule(n, e_n,
+                          (rho > 0.0 && rho < 1.0) ? tol * std::min(1.0, (1.0 - rho) / rho) : tol);
             // A convergent Dyson series has shrinking increments; a divergent one
             // grows them geometrically (the relative increment stays O(1)).
             grow = (n >= 2 && r[0] > d_prev) ? grow + 1 : 0;
+            if (grow > 0) plan.next = n + 1;
             if (grow >= 8) {
                 code = fail(SCD_EDIVERGED,
                             "sweep increments grew 8 times in a row (|dX|=%g, sweep %d)", r[0], n);
                 break;
             }
-            e_prev = e_n;
             d_prev = r[0];
         }
-        res->X = cur;
+        if (code == SCD_ENOTCONV) {
+            double r[3];
+            if (reduce(r)) return SCD_EHIP;
+        }
+        res->X = (double2*)cur;
         res->sweeps = n > max_iter ? max_iter : n;
         res->err = e_n;
-        res->rho = rho;
+        res->rho = plan.rho;
         return code;
     }
 
@@ -346,16 +406,16 @@ struct Solver {
             a.sites = nullptr;
             a.n_sites = g.n_r;
             a.part_off = 0;
+            a.check = 1;
             a.lc_sweep = cone ? radius_x : -1;
-            SCD_HIP(hipEventRecord(ev.a, st), "event record");
+            SCD_HIP(t64.mark(st), "event record");
             SCD_HIP(launch_residual_f64(g, a, St, S, src_blk, X, R32, partial, st),
                     "residual launch");
-            SCD_HIP(hipEventRecord(ev.b, st), "event record");
-            double r[3], secs;
-            if (reduce(r) || elapsed(&secs)) return SCD_EHIP;
+            SCD_HIP(t64.mark(st), "event record");
+            double r[3];
+            if (reduce(r)) return SCD_EHIP;
             stats->fp64_sweeps++;
             stats->sweep_launches++;
-            stats->sweep_kernel_seconds += secs;
             stats->gemm_flops += sweep_flops(cone ? radius_x + 1 : 1 << 20, cps);
             if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
                 code = fail(SCD_ENAN, "NaN or Inf in the FP64 residual at refinement step %d",
@@ -387,40 +447,24 @@ struct Solver {
             void* dn = D1;
             double e_prev = 0.0;
             int j = 0, stall = 0, half = radius_r;
+            CheckPlan plan;
             for (j = 1; j <= max_inner; ++j) {
-                double secs_sum = 0.0;
-                const int launches = red_black() ? 2 : 1;
-                int off = 0;
-                for (int c = 0; c < launches; ++c) {
-                    a.sites = red_black() ? colour_sites[c] : nullptr;
-                    a.n_sites = red_black() ? n_colour[c] : g.n_r;
-                    a.part_off = off;
-                    a.lc_sweep = cone ? half : -1;
-                    SCD_HIP(hipEventRecord(ev.a, st), "event record");
-                    SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, dc,
-                                               red_black() ? dc : dn, partial, st),
-                            "correct launch");
-                    SCD_HIP(hipEventRecord(ev.b, st), "event record");
-                    SCD_HIP(hipEventSynchronize(ev.b), "event sync");
-                    if (elapsed(&secs)) return SCD_EHIP;
-                    secs_sum += secs;
-                    stats->lowp_launches++;
-                    stats->gemm_flops +=
-                        sweep_flops(cone ? half + 1 : 1 << 20, cps, red_black() ? 1 + c : 0);
-                    off += a.n_sites * a.ntn;
-                    ++half;
-                }
-                if (reduce(r)) return SCD_EHIP;
+                a.check = (plan.due(j) || j == max_inner) ? 1 : 0;
+                if (sweep(a, true, src_blk, dc, dn, R32, cps, &half)) return SCD_EHIP;
                 if (!red_black()) std::swap(dc, dn);
                 stats->lowp_sweeps++;
-                stats->lowp_kernel_seconds += secs_sum;
+                if (!a.check) continue;
+                if (reduce(r)) return SCD_EHIP;
                 if (r[2] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[1])) {
                     code = fail(SCD_ENAN, "NaN or Inf in an FP32 correction sweep");
                     break;
                 }
                 const double e_in = r[1] > 0.0 ? r[0] / r[1] : 0.0;
-                if (j >= 2 && e_prev > 0.0 && e_in < e_prev) rho = e_in / e_prev;
+                plan.record(j, e_in);
+                plan.schedule(j, e_in, inner_tol);
+                if (plan.rho > 0.0 && plan.rho < 1.0) rho = plan.rho;
                 stall = (j >= 2 && e_in >= e_prev) ? stall + 1 : 0;
+                if (stall > 0) plan.next = j + 1;
                 e_prev = e_in;
                 if (e_in <= inner_tol || stall >= 3) break;
             }
@@ -551,7 +595,6 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     if (sv.St32)
         SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
-    SCD_HIP(sv.ev.create(), "event create");
 
     const int bs_max = block_sites < n_src ? block_sites : n_src;
     double worst_err = 0.0, worst_rho = 0.0;
@@ -575,6 +618,7 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         a.sites = nullptr;
         a.n_sites = g.n_r;
         a.part_off = 0;
+        a.check = 1;
         sv.pair_counts(src + blk_start, bs);
         double2* X = (double2*)(base + L.off_x0);
         double2* Xn = L.off_x1 ? (double2*)(base + L.off_x1) : nullptr;
@@ -742,7 +786,6 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
     sv.partial = (double*)(base + L.off_partial);
     sv.slot = (unsigned long long*)(base + L.off_slot);
     sv.nwg = L.nwg;
-    SCD_HIP(sv.ev.create(), "event create");
     sv.pair_counts(ident.data(), g.n_r);
     std::vector<int32_t> order;
     if (lattice_bipartite(g)) {
@@ -778,6 +821,7 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
         a.sites = nullptr;
         a.n_sites = g.n_r;
         a.part_off = 0;
+        a.check = 1;
         sv.St = pass == 0 ? St : StT;
         sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + (pass == 0 ? L.off_st32 : L.off_stt32))
                                         : nullptr;

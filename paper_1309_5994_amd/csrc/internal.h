@@ -5,7 +5,7 @@
 #include <cstddef>
 #include <cstdint>
 
-#include "../../include/scdyson.h"
+#include "scdyson.h"
 
 namespace scd {
 
@@ -47,6 +47,7 @@ struct SweepArgs {
                        // sweep), or nullptr for all sites in index order
     int n_sites;    // number of updated sites
     int part_off;   // offset (in workgroups) of this launch's convergence partials
+    int check;      // 1: read old values and reduce the increment; 0: write only
 };
 
 // X0 of a column block (the preconditioned unit-vector bundle):

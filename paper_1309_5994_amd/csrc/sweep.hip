@@ -30,6 +30,11 @@
 // neighbour tiles of the other colour); two such launches form a Gauss-Seidel
 // sweep, whose contraction rate is the square of the Jacobi sweep's.
 //
+// Convergence checks: a launch with `check` set reads each output's old value
+// and reduces max|X' - X|; other launches only write (plus max|X'| and the
+// NaN/Inf flag), which saves one tile read per workgroup.  The host schedules
+// checks from the measured contraction rate.
+//
 // Modes:
 //  * SOLVE     (FP64): X0 from S; writes Y; partials max|Y - X|, max|Y|.
 //  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64; partials
@@ -235,12 +240,17 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
                 const int row = (t0 + t) * kTile + E::row(v, lq);
                 const size_t off = (size_t)row * ldx + col;
                 double re = (double)accr[t][v], im = (double)acci[t][v];
-                const cplx old = Xi[off];
+                // The old value is needed for the increment only (RESIDUAL always
+                // needs it); sweeps that are not convergence checks skip the read.
+                const bool need_old = (MODE == MODE_RESIDUAL) || g.check;
+                const cplx old = need_old ? Xi[off] : cplx{0, 0};
                 if (MODE == MODE_CORRECT) {
                     const fvec2 r0 = R[site_off + off];
                     const float yr = (float)re + r0.x, yi = (float)im + r0.y;
                     reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{yr, yi};
-                    mdiff = fmax(mdiff, (double)fmaxf(fabsf(yr - (float)old.x), fabsf(yi - (float)old.y)));
+                    if (need_old)
+                        mdiff = fmax(mdiff, (double)fmaxf(fabsf(yr - (float)old.x),
+                                                          fabsf(yi - (float)old.y)));
                     mabs = fmax(mabs, (double)fmaxf(fabsf(yr), fabsf(yi)));
                     if (!(isfinite(yr) && isfinite(yi))) bad = 1.0;
                 } else {
@@ -262,7 +272,7 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
                     } else {
                         reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
                     }
-                    mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
+                    if (need_old) mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
                     mabs = fmax(mabs, fmax(fabs(re), fabs(im)));
                     if (!(isfinite(re) && isfinite(im))) bad = 1.0;
                 }

@@ -13,7 +13,7 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libscdyson.so")
+LIB_PATH = os.environ.get("SCD_LIBRARY") or os.path.join(_HERE, "libscdyson.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "scdyson.h")
 
 SCD_OK, SCD_EINVAL, SCD_ENOMEM, SCD_EHIP, SCD_ENOTCONV, SCD_EDIVERGED, SCD_ENAN = 0, -1, -2, -3, -4, -5, -6
@@ -64,7 +64,8 @@ _vp = ctypes.c_void_p
 
 
 def lib():
-    """Load libscdyson.so (once).  Raises if it has not been built."""
+    """Load libscdyson.so (once; SCD_LIBRARY may name another build).  Raises if it
+    has not been built."""
     global _lib
     if _lib is not None:
         return _lib

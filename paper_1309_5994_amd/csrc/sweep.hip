@@ -16,9 +16,12 @@
 //    tiles X_k[c-chunk][64 cols] are staged through LDS; the neighbour sum is
 //    the hopping stencil, done while staging so the summed tile never reaches
 //    HBM.  Global loads of chunk k+1 are issued before the MFMAs of chunk k.
-//  * complex products as four real MFMAs per 16x16x4 block
-//    (re += ar br - ai bi, im += ar bi + ai br) on
-//    V_MFMA_F64_16X16X4_F64 (FP64) or V_MFMA_F32_16X16X4_F32 (FP32).
+//  * complex products as real MFMAs per 16x16x4 block on
+//    V_MFMA_F64_16X16X4_F64 (FP64) or V_MFMA_F32_16X16X4_F32 (FP32): four
+//    (re += ar br - ai bi, im += ar bi + ai br), or three in Gauss's form
+//    (T = ar (br + bi), U = (ar + ai) bi, V = (ai - ar) br; re = T - U,
+//    im = T + V) where the third accumulator fits in registers.  Flops are
+//    counted as 8 per complex multiply-add either way.
 //  * light cone: after n sweeps the iterate of source j is zero beyond
 //    Manhattan distance n from j (the support argument of Sec. IV.D); a tile
 //    whose sources are all farther than n+1 from site i is skipped (its output
@@ -57,8 +60,12 @@ struct EngF64 {
     typedef double real;
     typedef dvec2 cplx;
     typedef dvec4 acc;
-    // K chunk (contour points per LDS stage); must divide 16 * MT
-    static constexpr int kc(int) { return 16; }
+    // Three real products per complex one (Gauss) where the third accumulator
+    // still fits in 256 VGPRs without spills.
+    static constexpr bool gauss(int mt) { return mt <= 12; }
+    // K chunk (contour points per LDS stage); must divide 16 * MT.  Large
+    // Gauss tiles stage 8 points to leave registers for the accumulators.
+    static constexpr int kc(int mt) { return (mt >= 11 && (gauss(mt) || mt >= 14)) ? 8 : 16; }
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -71,6 +78,7 @@ struct EngF32 {
     typedef fvec2 cplx;
     typedef fvec4 acc;
     static constexpr int kc(int mt) { return mt % 2 == 0 ? 32 : 16; }
+    static constexpr bool gauss(int) { return false; }
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -151,11 +159,16 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     const cplx* Xk[4];
     for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * ldx : nullptr;
 
-    acc accr[MH], acci[MH];
+    // Four-product form: accr = sum ar br - ai bi, acci = sum ar bi + ai br.
+    // Gauss form (G3): accr = T = sum ar (br + bi), acci = U = sum (ar + ai) bi,
+    // accg = V = sum (ai - ar) br; then re = T - U, im = T + V.
+    constexpr bool G3 = E::gauss(MT);
+    acc accr[MH], acci[MH], accg[G3 ? MH : 1];
 #pragma unroll
     for (int t = 0; t < MH; ++t) {
         accr[t] = acc{0, 0, 0, 0};
         acci[t] = acc{0, 0, 0, 0};
+        if (G3) accg[t] = acc{0, 0, 0, 0};
     }
     const int t0 = grp ? MH : 0;
     const int ntile = grp ? MT - MH : MH;
@@ -203,18 +216,30 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
 #pragma unroll
                 for (int t = 0; t < MH; ++t)
                     if (t < ntile) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
+                if (G3) {
+                    const real bsum = b.x + b.y;
 #pragma unroll
-                for (int t = 0; t < MH; ++t) {
-                    if (t < ntile) {
-                        accr[t] = E::mma(a[t].x, b.x, accr[t]);
-                        acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                    for (int t = 0; t < MH; ++t) {
+                        if (t < ntile) {
+                            accr[t] = E::mma(a[t].x, bsum, accr[t]);
+                            acci[t] = E::mma(a[t].x + a[t].y, b.y, acci[t]);
+                            accg[t] = E::mma(a[t].y - a[t].x, b.x, accg[t]);
+                        }
                     }
-                }
+                } else {
 #pragma unroll
-                for (int t = 0; t < MH; ++t) {
-                    if (t < ntile) {
-                        accr[t] = E::mma(-a[t].y, b.y, accr[t]);
-                        acci[t] = E::mma(a[t].y, b.x, acci[t]);
+                    for (int t = 0; t < MH; ++t) {
+                        if (t < ntile) {
+                            accr[t] = E::mma(a[t].x, b.x, accr[t]);
+                            acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < MH; ++t) {
+                        if (t < ntile) {
+                            accr[t] = E::mma(-a[t].y, b.y, accr[t]);
+                            acci[t] = E::mma(a[t].y, b.x, acci[t]);
+                        }
                     }
                 }
             }
@@ -239,7 +264,14 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
             for (int v = 0; v < 4; ++v) {
                 const int row = (t0 + t) * kTile + E::row(v, lq);
                 const size_t off = (size_t)row * ldx + col;
-                double re = (double)accr[t][v], im = (double)acci[t][v];
+                double re, im;
+                if (G3) {
+                    re = (double)accr[t][v] - (double)acci[t][v];
+                    im = (double)accr[t][v] + (double)accg[t][v];
+                } else {
+                    re = (double)accr[t][v];
+                    im = (double)acci[t][v];
+                }
                 // The old value is needed for the increment only (RESIDUAL always
                 // needs it); sweeps that are not convergence checks skip the read.
                 const bool need_old = (MODE == MODE_RESIDUAL) || g.check;

@@ -78,7 +78,7 @@ struct EngF32 {
     typedef fvec2 cplx;
     typedef fvec4 acc;
     static constexpr int kc(int mt) { return mt % 2 == 0 ? 32 : 16; }
-    static constexpr bool gauss(int) { return false; }
+    static constexpr bool gauss(int) { return true; }
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }

@@ -156,10 +156,40 @@ int colour_patch(const Geom& g) {
     return 1;
 }
 
-std::vector<int32_t> colour_order(const Geom& g, int* n_even) {
+// The sweep kernel hands each XCD one contiguous eighth of a launch's tile
+// order, i.e. about one eighth of its site list.  Listing the site groups
+// round-robin over the eight eighths (group k into eighth k mod 8) gives every
+// XCD sites from all over the lattice, which keeps the XCDs balanced while the
+// light cone (Sec. IV.D) still leaves the lattice's edges idle.  Whole groups
+// move, so the sites that share an XCD's L2 stay neighbours; a partial group
+// stays last.
+void interleave_groups(int32_t* sites, int n, int group) {
+    const int full = n / group;
+    std::vector<int32_t> out;
+    out.reserve(n);
+    for (int x = 0; x < 8; ++x)
+        for (int k = x; k < full; k += 8)
+            out.insert(out.end(), sites + (size_t)k * group, sites + (size_t)(k + 1) * group);
+    out.insert(out.end(), sites + (size_t)full * group, sites + n);
+    std::memcpy(sites, out.data(), (size_t)n * sizeof(int32_t));
+}
+
+// Launch site order.  Bipartite lattices: the two colours, (x + y) even then
+// odd, each listed patch by patch (square patches of `patch` x `patch` sites,
+// x-major inside) so that consecutive workgroups share the neighbour tiles of
+// the other colour; *n_even is the size of the first colour.  Other lattices:
+// all sites in index order, *n_even = 0.  Each segment is then interleaved
+// over the XCDs in groups of `group` sites.
+std::vector<int32_t> colour_order(const Geom& g, int group, bool bipartite, int* n_even) {
     const int patch = colour_patch(g);
     std::vector<int32_t> order;
     order.reserve(g.n_r);
+    if (!bipartite) {
+        for (int i = 0; i < g.n_r; ++i) order.push_back(i);
+        *n_even = 0;
+        interleave_groups(order.data(), g.n_r, group);
+        return order;
+    }
     for (int c = 0; c < 2; ++c) {
         for (int bx = 0; bx < g.Lx; bx += patch)
             for (int by = 0; by < g.Ly; by += patch)
@@ -168,6 +198,8 @@ std::vector<int32_t> colour_order(const Geom& g, int* n_even) {
                         if ((x + y) % 2 == c) order.push_back(x * g.Ly + y);
         if (c == 0) *n_even = (int)order.size();
     }
+    interleave_groups(order.data(), *n_even, group);
+    interleave_groups(order.data() + *n_even, g.n_r - *n_even, group);
     return order;
 }
 
@@ -240,6 +272,7 @@ struct Solver {
     int nwg;
     const int* colour_sites[2] = {nullptr, nullptr};   // device site lists (red-black)
     int n_colour[2] = {0, 0};
+    const int* all_sites = nullptr;   // device list of all n_r sites (launches over every site)
     LaunchTimer t64, t32;
     std::vector<double> within[3];   // (target, source) pairs within distance d, cumulative:
                                      // [0] all targets, [1] even-colour, [2] odd-colour targets
@@ -298,7 +331,7 @@ struct Solver {
         const int launches = red_black() ? 2 : 1;
         int off = 0;
         for (int c = 0; c < launches; ++c) {
-            a.sites = red_black() ? colour_sites[c] : nullptr;
+            a.sites = red_black() ? colour_sites[c] : all_sites;
             a.n_sites = red_black() ? n_colour[c] : g.n_r;
             a.part_off = off;
             a.lc_sweep = cone ? *half : -1;
@@ -403,7 +436,7 @@ struct Solver {
         int outer = 0, code = SCD_ENOTCONV, grow = 0;
         const int max_inner = 1000;
         for (outer = 1; outer <= max_iter; ++outer) {
-            a.sites = nullptr;
+            a.sites = all_sites;
             a.n_sites = g.n_r;
             a.part_off = 0;
             a.check = 1;
@@ -578,14 +611,15 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
 
     SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
             "copy src");
-    std::vector<int32_t> order;
-    if (lattice_bipartite(g)) {
-        int n_even = 0;
-        order = colour_order(g, &n_even);
-        int* order_dev = (int*)(base + L.off_order);
-        SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
-                               hipMemcpyHostToDevice, st),
-                "copy colour order");
+    const bool bipartite = lattice_bipartite(g);
+    int n_even = 0;
+    const std::vector<int32_t> order = colour_order(g, site_group(g), bipartite, &n_even);
+    int* order_dev = (int*)(base + L.off_order);
+    SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "copy site order");
+    sv.all_sites = order_dev;
+    if (bipartite) {
         sv.colour_sites[0] = order_dev;
         sv.colour_sites[1] = order_dev + n_even;
         sv.n_colour[0] = n_even;
@@ -787,14 +821,15 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
     sv.slot = (unsigned long long*)(base + L.off_slot);
     sv.nwg = L.nwg;
     sv.pair_counts(ident.data(), g.n_r);
-    std::vector<int32_t> order;
-    if (lattice_bipartite(g)) {
-        int n_even = 0;
-        order = colour_order(g, &n_even);
-        int* order_dev = (int*)(base + L.off_order);
-        SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
-                               hipMemcpyHostToDevice, st),
-                "copy colour order");
+    const bool bipartite = lattice_bipartite(g);
+    int n_even = 0;
+    const std::vector<int32_t> order = colour_order(g, site_group(g), bipartite, &n_even);
+    int* order_dev = (int*)(base + L.off_order);
+    SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "copy site order");
+    sv.all_sites = order_dev;
+    if (bipartite) {
         sv.colour_sites[0] = order_dev;
         sv.colour_sites[1] = order_dev + n_even;
         sv.n_colour[0] = n_even;

@@ -86,92 +86,55 @@ struct EngF32 {
     __device__ static int row(int v, int lq) { return 4 * lq + v; }
 };
 
-template <class E, int MT, int MODE>
-__global__ __launch_bounds__(kThreads)
-void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restrict__ S,
-                  const int* __restrict__ src_blk, const typename E::cplx* X, void* out,
-                  const fvec2* __restrict__ R,
-                  double* __restrict__ partial, SweepArgs g) {
+// Everything a wave does after the workgroup set-up, for a wave owning NT row
+// tiles from tile t0 on.  NT is a compile-time count: the kernel picks the
+// instantiation with one wave-uniform branch, so the MFMA stream carries no
+// per-tile predicates (those split each k-step into basic blocks that stop LDS
+// reads from overlapping the MFMAs).  All waves of the workgroup take part in
+// staging and in the final reduction whatever their NT.
+template <class E, int MT, int MODE, int NT>
+__device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ Sti,
+                                           const typename E::cplx* const (&Xk)[4],
+                                           const dvec2* __restrict__ S,
+                                           const int* __restrict__ src_blk,
+                                           const typename E::cplx* X, void* out,
+                                           const fvec2* __restrict__ R, double* part,
+                                           const SweepArgs& g, int i, int n0, int cols_per_src,
+                                           int t0, typename E::cplx* As, typename E::cplx* Bs,
+                                           double (*red)[3]) {
     typedef typename E::real real;
     typedef typename E::cplx cplx;
     typedef typename E::acc acc;
     constexpr int KC = E::kc(MT);
     constexpr int MP = kTile * MT;
     constexpr int NW = kColsPerWG;
-    constexpr int MH = (MT + 1) / 2;                 // row tiles of the upper wave group
     constexpr int A_ELEMS = KC * MP;
     constexpr int A_PER = (A_ELEMS + kThreads - 1) / kThreads;
     constexpr int B_ELEMS = KC * NW;
     constexpr int B_PER = B_ELEMS / kThreads;
+    constexpr int NA = NT > 0 ? NT : 1;
     static_assert(MP % KC == 0, "k chunk must tile the padded contour length");
     static_assert(B_ELEMS % kThreads == 0, "B chunk must be a whole number of passes");
-
-    // Native vector types (not HIP_vector_type) keep the staging arrays in registers.
-    __shared__ cplx As[A_PER * kThreads];   // [KC][MP] + padding of the last pass
-    __shared__ cplx Bs[B_ELEMS];            // [KC][NW]
-    __shared__ double red[kThreads / 64][3];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int grp = wave >> 2;
     const int wc = wave & 3;
     const int l16 = lane & 15;
     const int lq = lane >> 4;
-
-    const int tile = xcd_remap(blockIdx.x, gridDim.x);
-    int i, ct;
-    tile_site_col(tile, g.ntn, g.n_sites, g.group, &i, &ct);
-    if (g.sites) i = g.sites[i];
-    double* part = partial + 3 * (size_t)g.part_off;
-    const int n0 = ct * NW;
     const int ldx = g.ldx;
-    const int cols_per_src = (g.x0_kind == X0_BLOCK) ? g.n_t : 1;
-
-    int nb[4];
-    site_neighbours(i, g.Lx, g.Ly, g.periodic, nb);
-
-    // Light-cone skip (uniform per workgroup).
-    if (g.lc_sweep >= 0) {
-        const int s_lo = n0 / cols_per_src;
-        int s_hi = (n0 + NW - 1) / cols_per_src;
-        if (s_hi > g.bs - 1) s_hi = g.bs - 1;
-        const int xi = i / g.Ly, yi = i - (i / g.Ly) * g.Ly;
-        int dmin = 1 << 30;
-        for (int s = s_lo; s <= s_hi; ++s) {
-            const int j = src_blk[s];
-            const int xj = j / g.Ly, yj = j - (j / g.Ly) * g.Ly;
-            int dx = xi > xj ? xi - xj : xj - xi;
-            int dy = yi > yj ? yi - yj : yj - yi;
-            if (g.periodic) {
-                dx = dx < g.Lx - dx ? dx : g.Lx - dx;
-                dy = dy < g.Ly - dy ? dy : g.Ly - dy;
-            }
-            dmin = dmin < dx + dy ? dmin : dx + dy;
-        }
-        if (s_lo >= g.bs || dmin > g.lc_sweep + 1) {
-            if (tid < 3) part[3 * blockIdx.x + tid] = 0.0;
-            return;
-        }
-    }
-
-    const cplx* Sti = St + (size_t)i * MP * MP;
-    const cplx* Xk[4];
-    for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * ldx : nullptr;
 
     // Four-product form: accr = sum ar br - ai bi, acci = sum ar bi + ai br.
     // Gauss form (G3): accr = T = sum ar (br + bi), acci = U = sum (ar + ai) bi,
     // accg = V = sum (ai - ar) br; then re = T - U, im = T + V.
     constexpr bool G3 = E::gauss(MT);
-    acc accr[MH], acci[MH], accg[G3 ? MH : 1];
+    acc accr[NA], acci[NA], accg[G3 ? NA : 1];
 #pragma unroll
-    for (int t = 0; t < MH; ++t) {
+    for (int t = 0; t < NA; ++t) {
         accr[t] = acc{0, 0, 0, 0};
         acci[t] = acc{0, 0, 0, 0};
         if (G3) accg[t] = acc{0, 0, 0, 0};
     }
-    const int t0 = grp ? MH : 0;
-    const int ntile = grp ? MT - MH : MH;
 
     cplx ra[A_PER];
     cplx rb[B_PER][4];
@@ -209,38 +172,29 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
         if (k0 + KC < MP) SCD_GLOAD(k0 + KC);
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
-            {
-                const int kr = 4 * s + lq;
-                const cplx b = Bs[kr * NW + wc * 16 + l16];
-                cplx a[MH];
+            const int kr = 4 * s + lq;
+            const cplx b = Bs[kr * NW + wc * 16 + l16];
+            cplx a[NA];
 #pragma unroll
-                for (int t = 0; t < MH; ++t)
-                    if (t < ntile) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
-                if (G3) {
-                    const real bsum = b.x + b.y;
+            for (int t = 0; t < NT; ++t) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
+            if (G3) {
+                const real bsum = b.x + b.y;
 #pragma unroll
-                    for (int t = 0; t < MH; ++t) {
-                        if (t < ntile) {
-                            accr[t] = E::mma(a[t].x, bsum, accr[t]);
-                            acci[t] = E::mma(a[t].x + a[t].y, b.y, acci[t]);
-                            accg[t] = E::mma(a[t].y - a[t].x, b.x, accg[t]);
-                        }
-                    }
-                } else {
+                for (int t = 0; t < NT; ++t) {
+                    accr[t] = E::mma(a[t].x, bsum, accr[t]);
+                    acci[t] = E::mma(a[t].x + a[t].y, b.y, acci[t]);
+                    accg[t] = E::mma(a[t].y - a[t].x, b.x, accg[t]);
+                }
+            } else {
 #pragma unroll
-                    for (int t = 0; t < MH; ++t) {
-                        if (t < ntile) {
-                            accr[t] = E::mma(a[t].x, b.x, accr[t]);
-                            acci[t] = E::mma(a[t].x, b.y, acci[t]);
-                        }
-                    }
+                for (int t = 0; t < NT; ++t) {
+                    accr[t] = E::mma(a[t].x, b.x, accr[t]);
+                    acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                }
 #pragma unroll
-                    for (int t = 0; t < MH; ++t) {
-                        if (t < ntile) {
-                            accr[t] = E::mma(-a[t].y, b.y, accr[t]);
-                            acci[t] = E::mma(a[t].y, b.x, acci[t]);
-                        }
-                    }
+                for (int t = 0; t < NT; ++t) {
+                    accr[t] = E::mma(-a[t].y, b.y, accr[t]);
+                    acci[t] = E::mma(a[t].y, b.x, acci[t]);
                 }
             }
         }
@@ -258,56 +212,54 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     const size_t site_off = (size_t)i * MP * ldx;
     double mdiff = 0.0, mabs = 0.0, bad = 0.0;
 #pragma unroll
-    for (int t = 0; t < MH; ++t) {
-        if (t < ntile) {
+    for (int t = 0; t < NT; ++t) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = (t0 + t) * kTile + E::row(v, lq);
-                const size_t off = (size_t)row * ldx + col;
-                double re, im;
-                if (G3) {
-                    re = (double)accr[t][v] - (double)acci[t][v];
-                    im = (double)accr[t][v] + (double)accg[t][v];
-                } else {
-                    re = (double)accr[t][v];
-                    im = (double)acci[t][v];
+        for (int v = 0; v < 4; ++v) {
+            const int row = (t0 + t) * kTile + E::row(v, lq);
+            const size_t off = (size_t)row * ldx + col;
+            double re, im;
+            if (G3) {
+                re = (double)accr[t][v] - (double)acci[t][v];
+                im = (double)accr[t][v] + (double)accg[t][v];
+            } else {
+                re = (double)accr[t][v];
+                im = (double)acci[t][v];
+            }
+            // The old value is needed for the increment only (RESIDUAL always
+            // needs it); sweeps that are not convergence checks skip the read.
+            const bool need_old = (MODE == MODE_RESIDUAL) || g.check;
+            const cplx old = need_old ? Xi[off] : cplx{0, 0};
+            if (MODE == MODE_CORRECT) {
+                const fvec2 r0 = R[site_off + off];
+                const float yr = (float)re + r0.x, yi = (float)im + r0.y;
+                reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{yr, yi};
+                if (need_old)
+                    mdiff = fmax(mdiff, (double)fmaxf(fabsf(yr - (float)old.x),
+                                                      fabsf(yi - (float)old.y)));
+                mabs = fmax(mabs, (double)fmaxf(fabsf(yr), fabsf(yi)));
+                if (!(isfinite(yr) && isfinite(yi))) bad = 1.0;
+            } else {
+                if (own && row < g.n_t) {
+                    dvec2 s0;
+                    if (g.x0_kind == X0_COL_T)
+                        s0 = Si[(size_t)g.x0_fixed * g.n_t + row];
+                    else if (g.x0_kind == X0_COL)
+                        s0 = Si[(size_t)row * g.n_t + g.x0_fixed];
+                    else
+                        s0 = Si[(size_t)row * g.n_t + bcol];
+                    re += s0.x;
+                    im += s0.y;
                 }
-                // The old value is needed for the increment only (RESIDUAL always
-                // needs it); sweeps that are not convergence checks skip the read.
-                const bool need_old = (MODE == MODE_RESIDUAL) || g.check;
-                const cplx old = need_old ? Xi[off] : cplx{0, 0};
-                if (MODE == MODE_CORRECT) {
-                    const fvec2 r0 = R[site_off + off];
-                    const float yr = (float)re + r0.x, yi = (float)im + r0.y;
-                    reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{yr, yi};
-                    if (need_old)
-                        mdiff = fmax(mdiff, (double)fmaxf(fabsf(yr - (float)old.x),
-                                                          fabsf(yi - (float)old.y)));
-                    mabs = fmax(mabs, (double)fmaxf(fabsf(yr), fabsf(yi)));
-                    if (!(isfinite(yr) && isfinite(yi))) bad = 1.0;
+                // max-norm over real components: no overflow before a true Inf
+                const double dr = re - (double)old.x, di = im - (double)old.y;
+                if (MODE == MODE_SOLVE) {
+                    reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{re, im};
                 } else {
-                    if (own && row < g.n_t) {
-                        dvec2 s0;
-                        if (g.x0_kind == X0_COL_T)
-                            s0 = Si[(size_t)g.x0_fixed * g.n_t + row];
-                        else if (g.x0_kind == X0_COL)
-                            s0 = Si[(size_t)row * g.n_t + g.x0_fixed];
-                        else
-                            s0 = Si[(size_t)row * g.n_t + bcol];
-                        re += s0.x;
-                        im += s0.y;
-                    }
-                    // max-norm over real components: no overflow before a true Inf
-                    const double dr = re - (double)old.x, di = im - (double)old.y;
-                    if (MODE == MODE_SOLVE) {
-                        reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{re, im};
-                    } else {
-                        reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
-                    }
-                    if (need_old) mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
-                    mabs = fmax(mabs, fmax(fabs(re), fabs(im)));
-                    if (!(isfinite(re) && isfinite(im))) bad = 1.0;
+                    reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
                 }
+                if (need_old) mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
+                mabs = fmax(mabs, fmax(fabs(re), fabs(im)));
+                if (!(isfinite(re) && isfinite(im))) bad = 1.0;
             }
         }
     }
@@ -328,6 +280,75 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
         for (int w = 0; w < kThreads / 64; ++w) m = fmax(m, red[w][tid]);
         part[3 * blockIdx.x + tid] = m;
     }
+}
+
+template <class E, int MT, int MODE>
+__global__ __launch_bounds__(kThreads)
+void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restrict__ S,
+                  const int* __restrict__ src_blk, const typename E::cplx* X, void* out,
+                  const fvec2* __restrict__ R,
+                  double* __restrict__ partial, SweepArgs g) {
+    typedef typename E::cplx cplx;
+    constexpr int MP = kTile * MT;
+    constexpr int NW = kColsPerWG;
+    constexpr int MH = (MT + 1) / 2;                 // row tiles of the upper wave group
+
+    constexpr int KC = E::kc(MT);
+    constexpr int A_PER = (KC * MP + kThreads - 1) / kThreads;
+    // Native vector types (not HIP_vector_type) keep the staging arrays in registers.
+    __shared__ cplx As[A_PER * kThreads];   // [KC][MP] + padding of the last pass
+    __shared__ cplx Bs[KC * NW];            // [KC][NW]
+    __shared__ double red[kThreads / 64][3];
+
+    const int tid = threadIdx.x;
+    const int tile = xcd_remap(blockIdx.x, gridDim.x);
+    int i, ct;
+    tile_site_col(tile, g.ntn, g.n_sites, g.group, &i, &ct);
+    if (g.sites) i = g.sites[i];
+    double* part = partial + 3 * (size_t)g.part_off;
+    const int n0 = ct * NW;
+    const int cols_per_src = (g.x0_kind == X0_BLOCK) ? g.n_t : 1;
+
+    int nb[4];
+    site_neighbours(i, g.Lx, g.Ly, g.periodic, nb);
+
+    // Light-cone skip (uniform per workgroup).
+    if (g.lc_sweep >= 0) {
+        const int s_lo = n0 / cols_per_src;
+        int s_hi = (n0 + NW - 1) / cols_per_src;
+        if (s_hi > g.bs - 1) s_hi = g.bs - 1;
+        const int xi = i / g.Ly, yi = i - (i / g.Ly) * g.Ly;
+        int dmin = 1 << 30;
+        for (int s = s_lo; s <= s_hi; ++s) {
+            const int j = src_blk[s];
+            const int xj = j / g.Ly, yj = j - (j / g.Ly) * g.Ly;
+            int dx = xi > xj ? xi - xj : xj - xi;
+            int dy = yi > yj ? yi - yj : yj - yi;
+            if (g.periodic) {
+                dx = dx < g.Lx - dx ? dx : g.Lx - dx;
+                dy = dy < g.Ly - dy ? dy : g.Ly - dy;
+            }
+            dmin = dmin < dx + dy ? dmin : dx + dy;
+        }
+        if (s_lo >= g.bs || dmin > g.lc_sweep + 1) {
+            if (tid < 3) part[3 * blockIdx.x + tid] = 0.0;
+            return;
+        }
+    }
+
+    const cplx* Sti = St + (size_t)i * MP * MP;
+    const cplx* Xk[4];
+    for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * g.ldx : nullptr;
+
+    // Waves 0-3 own row tiles [0, MH), waves 4-7 [MH, MT).  The group index is
+    // wave-uniform; readfirstlane makes the branch a scalar one.
+    const int grp = __builtin_amdgcn_readfirstlane(tid >> 8);
+    if (grp == 0)
+        sweep_rows<E, MT, MODE, MH>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
+                                    0, As, Bs, red);
+    else
+        sweep_rows<E, MT, MODE, MT - MH>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0,
+                                         cols_per_src, MH, As, Bs, red);
 }
 
 template <class E, int MODE>

@@ -14,7 +14,7 @@ namespace scd {
 constexpr int kTile = 16;
 constexpr int kMaxRowTiles = 16;
 constexpr int kMaxNt = kTile * kMaxRowTiles;     // 256
-constexpr int kColsPerWG = 64;                   // column tile of one sweep workgroup
+constexpr int kColsPerWG = 32;                   // column tile of one sweep workgroup
 
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 typedef float fvec2 __attribute__((ext_vector_type(2)));
@@ -36,8 +36,8 @@ struct Geom {
 struct SweepArgs {
     int Lx, Ly, periodic;
     int n_r, n_t;
-    int ldx;        // padded column count of the block iterate (multiple of 64)
-    int ntn;        // column tiles per site = ldx / 64
+    int ldx;        // padded column count of the block iterate (multiple of kColsPerWG)
+    int ntn;        // column tiles per site = ldx / kColsPerWG
     int bs;         // source sites in this block
     int lc_sweep;   // sweeps already applied (light cone radius) or -1 to disable skipping
     int group;      // tile order: groups of `group` consecutive sites, column tile major inside

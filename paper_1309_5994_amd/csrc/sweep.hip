@@ -7,15 +7,19 @@
 // site's scaled atomic Green's function stored transposed (see aux.hip).
 //
 // Work decomposition (gfx950, 64-wide waves):
-//  * one workgroup = one target site i and a 64-column tile of the block
-//    iterate, all mp = 16*MT contour rows; 8 waves: waves 0-3 own the upper
-//    row tiles and waves 4-7 the lower ones, each wave one 16-column slice, so
-//    every SIMD runs all MT row tiles of one slice.
+//  * one workgroup = one target site i and a 32-column tile of the block
+//    iterate, all mp = 16*MT contour rows; 4 waves (one per SIMD): waves 0-1
+//    own the upper MT/2 row tiles, waves 2-3 the lower MT/2, each wave one
+//    16-column slice; for odd MT the last row tile is split over the k-steps
+//    between the two groups, so every SIMD issues the same MFMA count.  At
+//    about 200 VGPRs per wave two workgroups share a CU, and one's barriers
+//    and staging overlap the other's MFMAs.
 //  * K loop over contour time c in chunks of KC: the chunk of St_i
 //    (contiguous KC x mp complex) and the sum of the (up to) four neighbour
-//    tiles X_k[c-chunk][64 cols] are staged through LDS; the neighbour sum is
-//    the hopping stencil, done while staging so the summed tile never reaches
-//    HBM.  Global loads of chunk k+1 are issued before the MFMAs of chunk k.
+//    tiles X_k[c-chunk][32 cols] are staged through double-buffered LDS (one
+//    barrier per chunk); the neighbour sum is the hopping stencil, done while
+//    staging so the summed tile never reaches HBM.  Global loads of chunk k+1
+//    are issued before the MFMAs of chunk k.
 //  * complex products as real MFMAs per 16x16x4 block on
 //    V_MFMA_F64_16X16X4_F64 (FP64) or V_MFMA_F32_16X16X4_F32 (FP32): four
 //    (re += ar br - ai bi, im += ar bi + ai br), or three in Gauss's form
@@ -53,7 +57,7 @@
 namespace scd {
 namespace {
 
-constexpr int kThreads = 512;
+constexpr int kThreads = 256;
 enum { MODE_SOLVE = 0, MODE_RESIDUAL = 1, MODE_CORRECT = 2 };
 
 struct EngF64 {
@@ -63,9 +67,6 @@ struct EngF64 {
     // Three real products per complex one (Gauss) where the third accumulator
     // still fits in 256 VGPRs without spills.
     static constexpr bool gauss(int mt) { return mt <= 12; }
-    // K chunk (contour points per LDS stage); must divide 16 * MT.  Large
-    // Gauss tiles stage 8 points to leave registers for the accumulators.
-    static constexpr int kc(int mt) { return (mt >= 11 && (gauss(mt) || mt >= 14)) ? 8 : 16; }
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -77,7 +78,6 @@ struct EngF32 {
     typedef float real;
     typedef fvec2 cplx;
     typedef fvec4 acc;
-    static constexpr int kc(int mt) { return mt % 2 == 0 ? 32 : 16; }
     static constexpr bool gauss(int) { return true; }
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -86,13 +86,39 @@ struct EngF32 {
     __device__ static int row(int v, int lq) { return 4 * lq + v; }
 };
 
-// Everything a wave does after the workgroup set-up, for a wave owning NT row
-// tiles from tile t0 on.  NT is a compile-time count: the kernel picks the
-// instantiation with one wave-uniform branch, so the MFMA stream carries no
-// per-tile predicates (those split each k-step into basic blocks that stop LDS
-// reads from overlapping the MFMAs).  All waves of the workgroup take part in
-// staging and in the final reduction whatever their NT.
-template <class E, int MT, int MODE, int NT>
+// K chunk of a sweep kernel: the largest of 32, 16, 8 contour points that
+// divides mp and keeps the workgroup's double-buffered LDS (St chunk plus
+// neighbour sum) within half of the CU's 160 KB, so two workgroups fit per CU.
+template <class C>
+constexpr int chunk_k(int mt) {
+    const int mp = kTile * mt;
+    for (int kc = 32; kc >= 8; kc /= 2) {
+        const int bytes = 2 * kc * (mp + kColsPerWG) * (int)sizeof(C);
+        if (mp % kc == 0 && bytes <= 78 * 1024) return kc;
+    }
+    return 8;
+}
+
+// Elements of one St staging buffer: the chunk padded to whole passes of the
+// workgroup, and at least half the 8 KB through which the two row groups
+// exchange the shared tile's partial sums (2 slices x 4 rows x re/im x 64
+// lanes of doubles) once both buffers are free.
+template <class C>
+constexpr int as_stride(int mt) {
+    const int chunk = (chunk_k<C>(mt) * kTile * mt + kThreads - 1) / kThreads * kThreads;
+    const int xch = 2 * 4 * 2 * 64 * (int)sizeof(double) / 2 / (int)sizeof(C);
+    return chunk > xch ? chunk : xch;
+}
+
+// Everything a wave does after the workgroup set-up.  Waves 0-1 form row
+// group 0 and waves 2-3 row group 1 (GRP, a template parameter: the kernel
+// picks the instantiation with one wave-uniform branch, so the MFMA stream
+// carries no predicates); wave & 1 picks the 16-column slice.  Each group owns
+// MT/2 row tiles; for odd MT the last tile is shared, group 0 taking the even
+// and group 1 the odd k-steps of every chunk, and group 1 hands its partial
+// sums to group 0 through LDS before the epilogue.  Both groups therefore
+// issue the same number of MFMAs per chunk and every SIMD stays busy.
+template <class E, int MT, int MODE, int GRP>
 __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ Sti,
                                            const typename E::cplx* const (&Xk)[4],
                                            const dvec2* __restrict__ S,
@@ -100,29 +126,37 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                                            const typename E::cplx* X, void* out,
                                            const fvec2* __restrict__ R, double* part,
                                            const SweepArgs& g, int i, int n0, int cols_per_src,
-                                           int t0, typename E::cplx* As, typename E::cplx* Bs,
+                                           typename E::cplx* As, typename E::cplx* Bs,
                                            double (*red)[3]) {
     typedef typename E::real real;
     typedef typename E::cplx cplx;
     typedef typename E::acc acc;
-    constexpr int KC = E::kc(MT);
+    constexpr int KC = chunk_k<cplx>(MT);
     constexpr int MP = kTile * MT;
     constexpr int NW = kColsPerWG;
+    constexpr int NOWN = MT / 2;                      // row tiles owned by each group
+    constexpr bool SHARED = (MT % 2) != 0;            // last tile split over k-steps
+    constexpr int NA = NOWN + (SHARED ? 1 : 0);       // accumulator tiles per wave
     constexpr int A_ELEMS = KC * MP;
+    // The St chunk goes through registers, A_PER elements per thread; each of
+    // the two LDS buffers holds A_STRIDE elements (the chunk plus padding of
+    // the last pass).
     constexpr int A_PER = (A_ELEMS + kThreads - 1) / kThreads;
+    constexpr int A_STRIDE = as_stride<cplx>(MT);
     constexpr int B_ELEMS = KC * NW;
     constexpr int B_PER = B_ELEMS / kThreads;
-    constexpr int NA = NT > 0 ? NT : 1;
     static_assert(MP % KC == 0, "k chunk must tile the padded contour length");
     static_assert(B_ELEMS % kThreads == 0, "B chunk must be a whole number of passes");
+    static_assert((KC / 4) % 2 == 0, "the shared tile needs an even number of k-steps");
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int wc = wave & 3;
+    const int wc = wave & 1;
     const int l16 = lane & 15;
     const int lq = lane >> 4;
     const int ldx = g.ldx;
+    const int t0 = GRP * NOWN;                        // first owned row tile
 
     // Four-product form: accr = sum ar br - ai bi, acci = sum ar bi + ai br.
     // Gauss form (G3): accr = T = sum ar (br + bi), acci = U = sum (ar + ai) bi,
@@ -139,10 +173,12 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     cplx ra[A_PER];
     cplx rb[B_PER][4];
 
-    // Staging of one K chunk: global -> registers (issued a chunk ahead) and
-    // registers -> LDS.  Threads past the end of the A chunk re-load its last
-    // element into LDS padding, so no lane is predicated off.
-#define SCD_GLOAD(k0)                                                                  \
+    // Staging of one K chunk: global -> registers, issued a chunk ahead of its
+    // use, then registers -> LDS buffer `buf` (the St chunk as is, the four
+    // neighbour tiles summed).  Threads past the end of the St chunk re-load
+    // its last element into the buffer's padding, so no lane is predicated
+    // off.
+#define SCD_GLOAD(k0, buf)                                                             \
     do {                                                                               \
         _Pragma("unroll") for (int r = 0; r < A_PER; ++r) {                            \
             int e = tid + r * kThreads;                                                \
@@ -157,44 +193,63 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                 rb[r][d] = Xk[d] ? Xk[d][off] : cplx{0, 0};                            \
         }                                                                              \
     } while (0)
-#define SCD_LSTORE()                                                                   \
+#define SCD_LSTORE(buf)                                                                \
     do {                                                                               \
-        _Pragma("unroll") for (int r = 0; r < A_PER; ++r) As[tid + r * kThreads] = ra[r]; \
+        _Pragma("unroll") for (int r = 0; r < A_PER; ++r)                              \
+            As[(buf) * A_STRIDE + tid + r * kThreads] = ra[r];                         \
         _Pragma("unroll") for (int r = 0; r < B_PER; ++r)                              \
-            Bs[tid + r * kThreads] = (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);    \
+            Bs[(buf) * B_ELEMS + tid + r * kThreads] =                                 \
+                (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);                         \
     } while (0)
 
-    SCD_GLOAD(0);
-    for (int k0 = 0; k0 < MP; k0 += KC) {
+    // Double-buffered LDS, one barrier per chunk: the barrier of chunk c
+    // publishes its staged St chunk and neighbour sum, and proves every wave
+    // done with chunk c - 1, whose buffers chunk c + 1 then overwrites.
+    SCD_GLOAD(0, 0);
+    for (int k0 = 0, cb = 0; k0 < MP; k0 += KC, cb ^= 1) {
+        SCD_LSTORE(cb);
         __syncthreads();
-        SCD_LSTORE();
-        __syncthreads();
-        if (k0 + KC < MP) SCD_GLOAD(k0 + KC);
+        if (k0 + KC < MP) SCD_GLOAD(k0 + KC, cb ^ 1);
+        const cplx* Ac = As + cb * A_STRIDE;
+        const cplx* Bc = Bs + cb * B_ELEMS;
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
+            // Tiles of this k-step: the owned ones, plus the shared one on
+            // this group's parity.
+            const bool sh = SHARED && ((s & 1) == GRP);
+            const int nt = NOWN + (sh ? 1 : 0);
             const int kr = 4 * s + lq;
-            const cplx b = Bs[kr * NW + wc * 16 + l16];
+            const cplx b = Bc[kr * NW + wc * 16 + l16];
             cplx a[NA];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) a[t] = As[kr * MP + (t0 + t) * kTile + l16];
+            for (int t = 0; t < NA; ++t) {
+                const int tt = t < NOWN ? t0 + t : MT - 1;
+                if (t < nt) a[t] = Ac[kr * MP + tt * kTile + l16];
+            }
             if (G3) {
                 const real bsum = b.x + b.y;
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    accr[t] = E::mma(a[t].x, bsum, accr[t]);
-                    acci[t] = E::mma(a[t].x + a[t].y, b.y, acci[t]);
-                    accg[t] = E::mma(a[t].y - a[t].x, b.x, accg[t]);
+                for (int t = 0; t < NA; ++t) {
+                    if (t < nt) {
+                        accr[t] = E::mma(a[t].x, bsum, accr[t]);
+                        acci[t] = E::mma(a[t].x + a[t].y, b.y, acci[t]);
+                        accg[t] = E::mma(a[t].y - a[t].x, b.x, accg[t]);
+                    }
                 }
             } else {
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    accr[t] = E::mma(a[t].x, b.x, accr[t]);
-                    acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                for (int t = 0; t < NA; ++t) {
+                    if (t < nt) {
+                        accr[t] = E::mma(a[t].x, b.x, accr[t]);
+                        acci[t] = E::mma(a[t].x, b.y, acci[t]);
+                    }
                 }
 #pragma unroll
-                for (int t = 0; t < NT; ++t) {
-                    accr[t] = E::mma(-a[t].y, b.y, accr[t]);
-                    acci[t] = E::mma(a[t].y, b.x, acci[t]);
+                for (int t = 0; t < NA; ++t) {
+                    if (t < nt) {
+                        accr[t] = E::mma(-a[t].y, b.y, accr[t]);
+                        acci[t] = E::mma(a[t].y, b.x, acci[t]);
+                    }
                 }
             }
         }
@@ -202,7 +257,39 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
 #undef SCD_GLOAD
 #undef SCD_LSTORE
 
-    // Epilogue.
+    // Complex partial sums of tile t, element v.
+    auto part_re = [&](int t, int v) -> double {
+        return G3 ? (double)accr[t][v] - (double)acci[t][v] : (double)accr[t][v];
+    };
+    auto part_im = [&](int t, int v) -> double {
+        return G3 ? (double)accr[t][v] + (double)accg[t][v] : (double)acci[t][v];
+    };
+
+    // Shared tile: group 1 hands its partial sums to group 0 (the As buffers
+    // are free once every wave is past the last chunk).
+    double* xch = reinterpret_cast<double*>(As);      // [wc][v][re, im][lane]
+    double sh_re[4] = {0, 0, 0, 0}, sh_im[4] = {0, 0, 0, 0};
+    if (SHARED) {
+        __syncthreads();
+        if (GRP == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                xch[((wc * 4 + v) * 2 + 0) * 64 + lane] = part_re(NOWN, v);
+                xch[((wc * 4 + v) * 2 + 1) * 64 + lane] = part_im(NOWN, v);
+            }
+        }
+        __syncthreads();
+        if (GRP == 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                sh_re[v] = part_re(NOWN, v) + xch[((wc * 4 + v) * 2 + 0) * 64 + lane];
+                sh_im[v] = part_im(NOWN, v) + xch[((wc * 4 + v) * 2 + 1) * 64 + lane];
+            }
+        }
+    }
+
+    // Epilogue: the owned tiles, and (group 0) the shared one.
+    constexpr int NOUT = NOWN + ((SHARED && GRP == 0) ? 1 : 0);
     const int col = n0 + wc * 16 + l16;
     const int s_src = col / cols_per_src;
     const int bcol = col - s_src * cols_per_src;
@@ -212,19 +299,14 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     const size_t site_off = (size_t)i * MP * ldx;
     double mdiff = 0.0, mabs = 0.0, bad = 0.0;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
+    for (int t = 0; t < NOUT; ++t) {
+        const int tt = t < NOWN ? t0 + t : MT - 1;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = (t0 + t) * kTile + E::row(v, lq);
+            const int row = tt * kTile + E::row(v, lq);
             const size_t off = (size_t)row * ldx + col;
-            double re, im;
-            if (G3) {
-                re = (double)accr[t][v] - (double)acci[t][v];
-                im = (double)accr[t][v] + (double)accg[t][v];
-            } else {
-                re = (double)accr[t][v];
-                im = (double)acci[t][v];
-            }
+            double re = t < NOWN ? part_re(t, v) : sh_re[v];
+            double im = t < NOWN ? part_im(t, v) : sh_im[v];
             // The old value is needed for the increment only (RESIDUAL always
             // needs it); sweeps that are not convergence checks skip the read.
             const bool need_old = (MODE == MODE_RESIDUAL) || g.check;
@@ -283,7 +365,7 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
 }
 
 template <class E, int MT, int MODE>
-__global__ __launch_bounds__(kThreads)
+__global__ __launch_bounds__(kThreads, 2)
 void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restrict__ S,
                   const int* __restrict__ src_blk, const typename E::cplx* X, void* out,
                   const fvec2* __restrict__ R,
@@ -291,13 +373,12 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     typedef typename E::cplx cplx;
     constexpr int MP = kTile * MT;
     constexpr int NW = kColsPerWG;
-    constexpr int MH = (MT + 1) / 2;                 // row tiles of the upper wave group
-
-    constexpr int KC = E::kc(MT);
-    constexpr int A_PER = (KC * MP + kThreads - 1) / kThreads;
-    // Native vector types (not HIP_vector_type) keep the staging arrays in registers.
-    __shared__ cplx As[A_PER * kThreads];   // [KC][MP] + padding of the last pass
-    __shared__ cplx Bs[KC * NW];            // [KC][NW]
+    constexpr int KC = chunk_k<cplx>(MT);
+    constexpr int A_STRIDE = as_stride<cplx>(MT);
+    // Two buffers each; native vector types (not HIP_vector_type) keep the
+    // staging arrays in registers.
+    __shared__ __attribute__((aligned(16))) cplx As[2 * A_STRIDE];   // [KC][MP] + padding
+    __shared__ cplx Bs[2 * KC * NW];                                  // [KC][NW]
     __shared__ double red[kThreads / 64][3];
 
     const int tid = threadIdx.x;
@@ -340,15 +421,15 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     const cplx* Xk[4];
     for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * g.ldx : nullptr;
 
-    // Waves 0-3 own row tiles [0, MH), waves 4-7 [MH, MT).  The group index is
-    // wave-uniform; readfirstlane makes the branch a scalar one.
-    const int grp = __builtin_amdgcn_readfirstlane(tid >> 8);
+    // Row group of the wave (wave-uniform; readfirstlane makes the branch a
+    // scalar one).
+    const int grp = __builtin_amdgcn_readfirstlane(tid >> 7);
     if (grp == 0)
-        sweep_rows<E, MT, MODE, MH>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
-                                    0, As, Bs, red);
+        sweep_rows<E, MT, MODE, 0>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
+                                   As, Bs, red);
     else
-        sweep_rows<E, MT, MODE, MT - MH>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0,
-                                         cols_per_src, MH, As, Bs, red);
+        sweep_rows<E, MT, MODE, 1>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
+                                   As, Bs, red);
 }
 
 template <class E, int MODE>

@@ -77,6 +77,25 @@ def test_dyson_full_matches_dense_oracle(wl, block, device):
     assert st["status"] == 0 and st["n_blocks"] == -(-wl.n_r // block)
 
 
+# Every contour length up to 256 points maps to its own kernel instantiation
+# (row tiles MT = ceil(N_t / 16), odd MT splitting its last tile over the two
+# wave groups); the tile counts not covered by the workloads above, in FP64 and
+# with the FP32 correction sweeps.
+@pytest.mark.parametrize("n_real,n_imag", [(20, 8), (30, 12), (40, 10), (50, 20), (70, 16),
+                                           (80, 30), (100, 20), (110, 20), (120, 16)],
+                         ids=lambda v: str(v))
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+def test_tile_counts_match_dense_oracle(n_real, n_imag, prec, device):
+    wl = W.custom(2, 2, n_real, n_imag, J0=0.1, seed=n_real)
+    c, S_ref, G = oracle_dense(wl)
+    sources = [3, 0, 2, 1]
+    prob, out, n, ek = _solve(wl, device, sources, 3, prec=prec)
+    cols_ref = dense_columns(G, wl.n_r, c.n_t, sources)
+    assert rel_maxnorm(_np(out["G_cols"]), cols_ref) <= (1e-12 if prec == 0 else 1e-10)
+    G_loc = O.local_blocks_from_dense(G, c.n_t, sources)
+    assert np.abs(n - O.occupancy(G_loc, c)).max() <= (1e-12 if prec == 0 else 1e-8)
+
+
 def test_zero_hopping_returns_sigma_after_one_sweep(device):
     wl = W.custom(3, 4, 5, 4, J0=0.0, seed=2)
     from paper_1309_5994_amd import scdyson as B

@@ -22,9 +22,9 @@
 //    are issued before the MFMAs of chunk k.
 //  * complex products as real MFMAs per 16x16x4 block on
 //    V_MFMA_F64_16X16X4_F64 (FP64) or V_MFMA_F32_16X16X4_F32 (FP32): four
-//    (re += ar br - ai bi, im += ar bi + ai br), or three in Gauss's form
-//    (T = ar (br + bi), U = (ar + ai) bi, V = (ai - ar) br; re = T - U,
-//    im = T + V) where the third accumulator fits in registers.  Flops are
+//    (re += ar br - ai bi, im += ar bi + ai br), or three (P1 = ar br,
+//    P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2, im = P3 - P1 - P2)
+//    where the third accumulator fits in registers.  Flops are
 //    counted as 8 per complex multiply-add either way.
 //  * light cone: after n sweeps the iterate of source j is zero beyond
 //    Manhattan distance n from j (the support argument of Sec. IV.D); a tile
@@ -64,9 +64,10 @@ struct EngF64 {
     typedef double real;
     typedef dvec2 cplx;
     typedef dvec4 acc;
-    // Three real products per complex one (Gauss) where the third accumulator
-    // still fits in 256 VGPRs without spills.
+    // Three real products per complex one where the third accumulator still
+    // fits in 256 VGPRs without spills; in the staged-sum form (P1, P2, P3).
     static constexpr bool gauss(int mt) { return mt <= 12; }
+    static constexpr bool staged_sum = true;
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -78,7 +79,10 @@ struct EngF32 {
     typedef float real;
     typedef fvec2 cplx;
     typedef fvec4 acc;
+    // Gauss's form (T, U, V) with its sums in the k-loop: the staged-sum form
+    // costs enough registers to drop a third FP32 workgroup per CU.
     static constexpr bool gauss(int) { return true; }
+    static constexpr bool staged_sum = false;
     __device__ static acc mma(real a, real b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -87,13 +91,17 @@ struct EngF32 {
 };
 
 // K chunk of a sweep kernel: the largest of 32, 16, 8 contour points that
-// divides mp and keeps the workgroup's double-buffered LDS (St chunk plus
-// neighbour sum) within half of the CU's 160 KB, so two workgroups fit per CU.
-template <class C>
+// divides mp and keeps the workgroup's double-buffered LDS (St chunk,
+// neighbour sum and its (br + bi) plane) within half of the CU's 160 KB, so
+// two workgroups fit per CU.
+template <class E>
 constexpr int chunk_k(int mt) {
+    typedef typename E::cplx C;
+    const bool staged = E::gauss(mt) && E::staged_sum;
     const int mp = kTile * mt;
     for (int kc = 32; kc >= 8; kc /= 2) {
-        const int bytes = 2 * kc * (mp + kColsPerWG) * (int)sizeof(C);
+        // St chunk, neighbour sum and its (br + bi) plane, two buffers each
+        const int bytes = kc * (2 * mp + (staged ? 3 : 2) * kColsPerWG) * (int)sizeof(C);
         if (mp % kc == 0 && bytes <= 78 * 1024) return kc;
     }
     return 8;
@@ -103,9 +111,10 @@ constexpr int chunk_k(int mt) {
 // workgroup, and at least half the 8 KB through which the two row groups
 // exchange the shared tile's partial sums (2 slices x 4 rows x re/im x 64
 // lanes of doubles) once both buffers are free.
-template <class C>
+template <class E>
 constexpr int as_stride(int mt) {
-    const int chunk = (chunk_k<C>(mt) * kTile * mt + kThreads - 1) / kThreads * kThreads;
+    typedef typename E::cplx C;
+    const int chunk = (chunk_k<E>(mt) * kTile * mt + kThreads - 1) / kThreads * kThreads;
     const int xch = 2 * 4 * 2 * 64 * (int)sizeof(double) / 2 / (int)sizeof(C);
     return chunk > xch ? chunk : xch;
 }
@@ -127,11 +136,11 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                                            const fvec2* __restrict__ R, double* part,
                                            const SweepArgs& g, int i, int n0, int cols_per_src,
                                            typename E::cplx* As, typename E::cplx* Bs,
-                                           double (*red)[3]) {
+                                           typename E::real* Bd, double (*red)[3]) {
     typedef typename E::real real;
     typedef typename E::cplx cplx;
     typedef typename E::acc acc;
-    constexpr int KC = chunk_k<cplx>(MT);
+    constexpr int KC = chunk_k<E>(MT);
     constexpr int MP = kTile * MT;
     constexpr int NW = kColsPerWG;
     constexpr int NOWN = MT / 2;                      // row tiles owned by each group
@@ -142,7 +151,7 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     // the two LDS buffers holds A_STRIDE elements (the chunk plus padding of
     // the last pass).
     constexpr int A_PER = (A_ELEMS + kThreads - 1) / kThreads;
-    constexpr int A_STRIDE = as_stride<cplx>(MT);
+    constexpr int A_STRIDE = as_stride<E>(MT);
     constexpr int B_ELEMS = KC * NW;
     constexpr int B_PER = B_ELEMS / kThreads;
     static_assert(MP % KC == 0, "k chunk must tile the padded contour length");
@@ -159,9 +168,14 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     const int t0 = GRP * NOWN;                        // first owned row tile
 
     // Four-product form: accr = sum ar br - ai bi, acci = sum ar bi + ai br.
-    // Gauss form (G3): accr = T = sum ar (br + bi), acci = U = sum (ar + ai) bi,
-    // accg = V = sum (ai - ar) br; then re = T - U, im = T + V.
+    // Three-product forms (G3).  Staged-sum form (E::staged_sum): accr = P1 =
+    // sum ar br, acci = P2 = sum ai bi, accg = P3 = sum (ar + ai)(br + bi);
+    // re = P1 - P2, im = P3 - P1 - P2; the (br + bi) plane is staged with the
+    // neighbour sum, so a k-step adds only one (ar + ai) per row tile in front
+    // of its MFMAs.  Gauss's form: accr = T = sum ar (br + bi), acci = U =
+    // sum (ar + ai) bi, accg = V = sum (ai - ar) br; re = T - U, im = T + V.
     constexpr bool G3 = E::gauss(MT);
+    constexpr bool PS = G3 && E::staged_sum;
     acc accr[NA], acci[NA], accg[G3 ? NA : 1];
 #pragma unroll
     for (int t = 0; t < NA; ++t) {
@@ -198,8 +212,11 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
         _Pragma("unroll") for (int r = 0; r < A_PER; ++r)                              \
             As[(buf) * A_STRIDE + tid + r * kThreads] = ra[r];                         \
         _Pragma("unroll") for (int r = 0; r < B_PER; ++r)                              \
-            Bs[(buf) * B_ELEMS + tid + r * kThreads] =                                 \
-                (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);                         \
+        {                                                                              \
+            const cplx v = (rb[r][0] + rb[r][1]) + (rb[r][2] + rb[r][3]);              \
+            Bs[(buf) * B_ELEMS + tid + r * kThreads] = v;                              \
+            if (PS) Bd[(buf) * B_ELEMS + tid + r * kThreads] = v.x + v.y;              \
+        }                                                                              \
     } while (0)
 
     // Double-buffered LDS, one barrier per chunk: the barrier of chunk c
@@ -212,6 +229,7 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
         if (k0 + KC < MP) SCD_GLOAD(k0 + KC, cb ^ 1);
         const cplx* Ac = As + cb * A_STRIDE;
         const cplx* Bc = Bs + cb * B_ELEMS;
+        const real* Bdc = Bd + cb * B_ELEMS;
 #pragma unroll
         for (int s = 0; s < KC / 4; ++s) {
             // Tiles of this k-step: the owned ones, plus the shared one on
@@ -226,7 +244,17 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                 const int tt = t < NOWN ? t0 + t : MT - 1;
                 if (t < nt) a[t] = Ac[kr * MP + tt * kTile + l16];
             }
-            if (G3) {
+            if (PS) {
+                const real bsum = Bdc[kr * NW + wc * 16 + l16];
+#pragma unroll
+                for (int t = 0; t < NA; ++t) {
+                    if (t < nt) {
+                        accr[t] = E::mma(a[t].x, b.x, accr[t]);
+                        acci[t] = E::mma(a[t].y, b.y, acci[t]);
+                        accg[t] = E::mma(a[t].x + a[t].y, bsum, accg[t]);
+                    }
+                }
+            } else if (G3) {
                 const real bsum = b.x + b.y;
 #pragma unroll
                 for (int t = 0; t < NA; ++t) {
@@ -262,7 +290,9 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
         return G3 ? (double)accr[t][v] - (double)acci[t][v] : (double)accr[t][v];
     };
     auto part_im = [&](int t, int v) -> double {
-        return G3 ? (double)accr[t][v] + (double)accg[t][v] : (double)acci[t][v];
+        return PS   ? (double)accg[t][v] - (double)accr[t][v] - (double)acci[t][v]
+               : G3 ? (double)accr[t][v] + (double)accg[t][v]
+                    : (double)acci[t][v];
     };
 
     // Shared tile: group 1 hands its partial sums to group 0 (the As buffers
@@ -373,12 +403,13 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     typedef typename E::cplx cplx;
     constexpr int MP = kTile * MT;
     constexpr int NW = kColsPerWG;
-    constexpr int KC = chunk_k<cplx>(MT);
-    constexpr int A_STRIDE = as_stride<cplx>(MT);
+    constexpr int KC = chunk_k<E>(MT);
+    constexpr int A_STRIDE = as_stride<E>(MT);
     // Two buffers each; native vector types (not HIP_vector_type) keep the
     // staging arrays in registers.
     __shared__ __attribute__((aligned(16))) cplx As[2 * A_STRIDE];   // [KC][MP] + padding
     __shared__ cplx Bs[2 * KC * NW];                                  // [KC][NW]
+    __shared__ typename E::real Bd[E::gauss(MT) && E::staged_sum ? 2 * KC * NW : 2];  // br + bi
     __shared__ double red[kThreads / 64][3];
 
     const int tid = threadIdx.x;
@@ -426,10 +457,10 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
     const int grp = __builtin_amdgcn_readfirstlane(tid >> 7);
     if (grp == 0)
         sweep_rows<E, MT, MODE, 0>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
-                                   As, Bs, red);
+                                   As, Bs, Bd, red);
     else
         sweep_rows<E, MT, MODE, 1>(Sti, Xk, S, src_blk, X, out, R, part, g, i, n0, cols_per_src,
-                                   As, Bs, red);
+                                   As, Bs, Bd, red);
 }
 
 template <class E, int MODE>

@@ -119,14 +119,15 @@ Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
 
 // Sites per tile-order group of the sweep kernel (see tile_site_col):
 // SCD_SITE_GROUP overrides; the default keeps a group's site operands
-// (mp^2 complex each) within about 2 MB of one XCD's L2.
+// (mp^2 complex each) within about 2.7 MB of one XCD's 4 MB L2 (measured
+// best on 16x16 / N_t = 144 and 24x24 / N_t = 176).
 int site_group(const Geom& g) {
     if (const char* env = std::getenv("SCD_SITE_GROUP")) {
         const int v = std::atoi(env);
         if (v >= 1) return v < g.n_r ? v : g.n_r;
     }
     const double per_site = (double)g.mp * g.mp * 16.0;
-    int grp = (int)(2.0e6 / per_site);
+    int grp = (int)(2.7e6 / per_site);
     if (grp < 1) grp = 1;
     if (grp > g.n_r) grp = g.n_r;
     return grp;
@@ -148,12 +149,14 @@ struct BlockResult {
 // Within a colour, sites are listed patch by patch (square patches of
 // `patch` x `patch` lattice sites, x-major inside), so that consecutive
 // workgroups of one launch share the neighbour tiles of the other colour.
+// SCD_PATCH overrides the default of 2 (a group of sites then covers a
+// two-row strip of the lattice, whose targets share most neighbours).
 int colour_patch(const Geom& g) {
     if (const char* env = std::getenv("SCD_PATCH")) {
         const int v = std::atoi(env);
         if (v >= 1) return v;
     }
-    return 1;
+    return 2;
 }
 
 // The sweep kernel hands each XCD one contiguous eighth of a launch's tile

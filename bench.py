@@ -22,16 +22,23 @@ sys.path.insert(0, ROOT)
 from paper_1309_5994_amd import workloads as W          # noqa: E402
 
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (MFMA = vector)
-SWEEP_SOURCE = os.path.join(ROOT, "paper_1309_5994_amd", "csrc", "sweep.hip")
+# The sweep kernel and the host code that orders its tiles (the site order
+# decides how much of the traffic the caches absorb).
+TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1309_5994_amd", "csrc", f)
+                   for f in ("sweep.hip", "api.hip")]
 PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_fp64_trap16x16_nt144.md")
 
 
 def measured_traffic():
     """HBM bytes per launch of the FP64 sweep kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source (else None)."""
+    counter summary, if it was taken on the current kernel and tile-order
+    sources (else None)."""
     import hashlib
     try:
-        sha = hashlib.sha256(open(SWEEP_SOURCE, "rb").read()).hexdigest()[:16]
+        h = hashlib.sha256()
+        for path in TRAFFIC_SOURCES:
+            h.update(open(path, "rb").read())
+        sha = h.hexdigest()[:16]
         for line in open(PROFILE):
             if line.startswith("traffic-record:"):
                 fields = dict(kv.split("=", 1) for kv in line.split()[1:])

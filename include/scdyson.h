@@ -60,6 +60,10 @@ extern "C" {
 /* Sweep precision for dyson_iterate. */
 #define SCD_PREC_FP64   0   /* complex128 sweeps on FP64 MFMA                   */
 #define SCD_PREC_FP32   1   /* complex64 FP32-MFMA correction sweeps + FP64 refinement */
+#define SCD_PREC_BF16X3 2   /* complex64 correction sweeps on BF16 MFMA with split
+                               products (x = hi + lo in bf16; a b ~ a_hi b_hi +
+                               a_hi b_lo + a_lo b_hi, FP32 accumulation; Henry, Tang
+                               & Heinecke, ARITH 2019) + FP64 refinement        */
 
 typedef struct scd_problem {
     int32_t Lx, Ly;      /* lattice extent                                      */
@@ -122,11 +126,11 @@ int sigma_build(const scd_problem* p, const double* V, const double* U, void* S,
  *   src        host int32[n_src]           source sites, each in [0, N_r)
  *   block_sites sources per column block (1..n_src); the block's iterate is
  *              N_r x N_t x block_sites*N_t complex, sized for HBM by the caller
- *   prec       SCD_PREC_FP64 or SCD_PREC_FP32
+ *   prec       SCD_PREC_FP64, SCD_PREC_FP32 or SCD_PREC_BF16X3
  *   tol        stop when the relative max-norm increment of a sweep (FP64) or
- *              the relative FP64 residual (FP32 + refinement) falls below tol,
+ *              the relative FP64 residual (FP32 / BF16x3 + refinement) falls below tol,
  *              with the contraction-corrected estimate e_n rho/(1-rho) also below tol
- *   max_iter   sweep limit per block (FP64 sweeps for SCD_PREC_FP32)
+ *   max_iter   sweep limit per block (FP64 sweeps for the refined precisions)
  *   G_cols     device complex128[N_r][N_t][n_src*N_t] or NULL: full columns,
  *              column (s, b) = source src[s], contour time b
  *   G_loc      device complex128[n_src][N_t][N_t]: G(src[s], src[s]) blocks

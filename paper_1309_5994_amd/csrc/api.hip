@@ -80,7 +80,8 @@ struct Layout {
 bool lattice_bipartite(const Geom& g) { return !g.periodic || (g.Lx % 2 == 0 && g.Ly % 2 == 0); }
 
 // Workspace: St (FP64 operand) and one FP64 iterate, updated in place by
-// red-black sweeps; FP32 path: + St32, the complex64 residual and one
+// red-black sweeps; refined paths: + the low-precision operand (complex64
+// St32 for FP32, six bf16 planes for BF16x3), the complex64 residual and one
 // correction.  A lattice that is not bipartite (periodic with an odd extent)
 // sweeps Jacobi-style and needs a second FP64 iterate (second correction).
 Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
@@ -104,7 +105,8 @@ Layout layout(const Geom& g, int n_src, int block_sites, int prec) {
     if (prec == SCD_PREC_FP64) {
         if (!rb) L.off_x1 = take(it64);
     } else {
-        L.off_st32 = take((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
+        L.off_st32 = take(prec == SCD_PREC_BF16X3 ? bf3_operand_bytes(g)
+                                                  : (size_t)g.n_r * g.mp * g.mp * sizeof(float2));
         L.off_r32 = take(it32);
         L.off_d0 = take(it32);
         if (!rb) L.off_d1 = take(it32);
@@ -268,7 +270,8 @@ struct Solver {
     hipStream_t st;
     scd_stats* stats;
     double2* St;
-    void* St32;
+    void* St32;         // low-precision operand (complex64, or BF16x3 planes)
+    bool bf3 = false;   // correction sweeps on the BF16x3 engine
     const double2* S;
     double* partial;
     unsigned long long* slot;
@@ -342,7 +345,8 @@ struct Solver {
             LaunchTimer& tm = fp32 ? t32 : t64;
             SCD_HIP(tm.mark(st), "event record");
             if (fp32)
-                SCD_HIP(launch_correct_f32(g, a, St32, src_blk, R32, cur, out, partial, st),
+                SCD_HIP(bf3 ? launch_correct_bf3(g, a, St32, src_blk, R32, cur, out, partial, st)
+                            : launch_correct_f32(g, a, St32, src_blk, R32, cur, out, partial, st),
                         "correct launch");
             else
                 SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, (const double2*)cur,
@@ -475,8 +479,9 @@ struct Solver {
             // outer target needs: the corrected X is off by about
             // eta |R| / (1 - rho) for a relative correction accuracy eta.
             const double rho_g = (rho > 0.0 && rho < 1.0) ? rho : 0.5;
+            const double floor = bf3 ? 3e-5 : 1e-6;   // accuracy of the correction engine
             const double inner_tol =
-                std::min(0.1, std::max(1e-6, 0.3 * tol * (1.0 - rho_g) / e_r));
+                std::min(0.1, std::max(floor, 0.3 * tol * (1.0 - rho_g) / e_r));
             const int radius_r = radius_x + 1;
             SCD_HIP(launch_copy_f32(R32, D0, n_elem, st), "copy launch");
             void* dc = D0;
@@ -530,7 +535,7 @@ int scd_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites
     if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
     if (n_src < 1 || n_src > g.n_r) return fail(SCD_EINVAL, "n_src must be in [1, N_r]");
     if (block_sites < 1) return fail(SCD_EINVAL, "block_sites must be >= 1");
-    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32 && prec != SCD_PREC_BF16X3)
         return fail(SCD_EINVAL, "unsupported precision %d", prec);
     *bytes = layout(g, n_src, block_sites, prec).total;
     g_last_error.clear();
@@ -587,7 +592,7 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         return finish(fail(SCD_EINVAL, "S, J, src, G_loc and ws must be non-NULL"));
     if (n_src < 1 || n_src > g.n_r) return finish(fail(SCD_EINVAL, "n_src must be in [1, N_r]"));
     if (block_sites < 1) return finish(fail(SCD_EINVAL, "block_sites must be >= 1"));
-    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32 && prec != SCD_PREC_BF16X3)
         return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
     if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
     if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
@@ -605,7 +610,8 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     sv.st = st;
     sv.stats = &stats;
     sv.St = (double2*)(base + L.off_st);
-    sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + L.off_st32) : nullptr;
+    sv.St32 = prec != SCD_PREC_FP64 ? (void*)(base + L.off_st32) : nullptr;
+    sv.bf3 = prec == SCD_PREC_BF16X3;
     sv.S = (const double2*)S;
     sv.partial = (double*)(base + L.off_partial);
     sv.slot = (unsigned long long*)(base + L.off_slot);
@@ -629,7 +635,9 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         sv.n_colour[1] = g.n_r - n_even;
     }
     SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, 0, st), "scale_transpose launch");
-    if (sv.St32)
+    if (sv.bf3)
+        SCD_HIP(launch_bf3_operand(g, sv.St, sv.St32, st), "BF16x3 operand launch");
+    else if (sv.St32)
         SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
 
@@ -710,7 +718,9 @@ AdjLayout adj_layout(const Geom& g, int prec) {
     L.ntn = L.ldx / kColsPerWG;
     L.nwg = g.n_r * L.ntn;
     const size_t op64 = align256((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
-    const size_t op32 = align256((size_t)g.n_r * g.mp * g.mp * sizeof(float2));
+    const size_t op32 = align256(prec == SCD_PREC_BF16X3
+                                     ? bf3_operand_bytes(g)
+                                     : (size_t)g.n_r * g.mp * g.mp * sizeof(float2));
     const size_t it64 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(double2));
     const size_t it32 = align256((size_t)g.n_r * g.mp * L.ldx * sizeof(float2));
     size_t off = 0;
@@ -754,7 +764,7 @@ int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* byte
     int rc = check_problem(p, kMaxNt, &g);
     if (rc) return rc;
     if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
-    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32 && prec != SCD_PREC_BF16X3)
         return fail(SCD_EINVAL, "unsupported precision %d", prec);
     *bytes = adj_layout(g, prec).total;
     g_last_error.clear();
@@ -788,7 +798,7 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
     if (!grads && !loss && !n_te) return finish(fail(SCD_EINVAL, "nothing to compute"));
     if (t_index < 0 || t_index >= g.n_real)
         return finish(fail(SCD_EINVAL, "t_index must be in [0, n_real)"));
-    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32)
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32 && prec != SCD_PREC_BF16X3)
         return finish(fail(SCD_EINVAL, "unsupported precision %d", prec));
     if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
     if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
@@ -808,10 +818,17 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
     double2* StT = (double2*)(base + L.off_stt);
     SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, St, 0, st), "operand launch");
     if (grads) SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, StT, 1, st), "operand launch");
-    if (prec == SCD_PREC_FP32) {
+    if (prec != SCD_PREC_FP64) {
         const size_t n_op = (size_t)g.n_r * g.mp * g.mp;
-        SCD_HIP(launch_to_f32(St, base + L.off_st32, n_op, st), "St32 launch");
-        if (grads) SCD_HIP(launch_to_f32(StT, base + L.off_stt32, n_op, st), "St32 launch");
+        if (prec == SCD_PREC_BF16X3) {
+            SCD_HIP(launch_bf3_operand(g, St, base + L.off_st32, st), "BF16x3 operand launch");
+            if (grads)
+                SCD_HIP(launch_bf3_operand(g, StT, base + L.off_stt32, st),
+                        "BF16x3 operand launch");
+        } else {
+            SCD_HIP(launch_to_f32(St, base + L.off_st32, n_op, st), "St32 launch");
+            if (grads) SCD_HIP(launch_to_f32(StT, base + L.off_stt32, n_op, st), "St32 launch");
+        }
     }
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
 
@@ -861,8 +878,9 @@ int dyson_adjoint(const scd_problem* p, const void* S, const double* V, const do
         a.part_off = 0;
         a.check = 1;
         sv.St = pass == 0 ? St : StT;
-        sv.St32 = prec == SCD_PREC_FP32 ? (void*)(base + (pass == 0 ? L.off_st32 : L.off_stt32))
+        sv.St32 = prec != SCD_PREC_FP64 ? (void*)(base + (pass == 0 ? L.off_st32 : L.off_stt32))
                                         : nullptr;
+        sv.bf3 = prec == SCD_PREC_BF16X3;
         double2* X = (double2*)(base + (pass == 0 ? L.off_xg : L.off_xh));
         double2* Xn = L.off_x1 ? (double2*)(base + L.off_x1) : nullptr;
         SCD_HIP(launch_init_block(g, (const double2*)S, src_dev, g.n_r, L.ldx, a.x0_kind,

@@ -120,6 +120,14 @@ hipError_t launch_correct_f32(const Geom& g, const SweepArgs& a, const void* St3
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st);
 hipError_t launch_to_f32(const double2* in, void* out, size_t n, hipStream_t st);
+// BF16x3 correction sweep (sweep_bf3.hip): operand bytes for g, operand build
+// from St (complex128 [n_r][mp][mp]), and the sweep D' = R + St^T N(D) with
+// one convergence partial per workgroup, as the other sweep launchers.
+size_t bf3_operand_bytes(const Geom& g);
+hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipStream_t st);
+hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
+                              const int* src_blk, const void* R32, const void* D32, void* Dn32,
+                              double* partial, hipStream_t st);
 hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st);
 hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st);
 hipError_t launch_adjoint_grads(const Geom& g, int ldx, int e, const double2* H, const double2* Gc,

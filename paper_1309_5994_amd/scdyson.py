@@ -17,7 +17,7 @@ LIB_PATH = os.environ.get("SCD_LIBRARY") or os.path.join(_HERE, "libscdyson.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "scdyson.h")
 
 SCD_OK, SCD_EINVAL, SCD_ENOMEM, SCD_EHIP, SCD_ENOTCONV, SCD_EDIVERGED, SCD_ENAN = 0, -1, -2, -3, -4, -5, -6
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 ERROR_NAMES = {0: "SCD_OK", -1: "SCD_EINVAL", -2: "SCD_ENOMEM", -3: "SCD_EHIP",
                -4: "SCD_ENOTCONV", -5: "SCD_EDIVERGED", -6: "SCD_ENAN"}
 

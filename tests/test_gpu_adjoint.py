@@ -35,7 +35,7 @@ CASES = [
 
 
 @pytest.mark.parametrize("wl,periodic", CASES, ids=["cfg1", "mod3x4", "mod_periodic4x3"])
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "mixed", "bf16x3"])
 def test_adjoint_matches_dense_oracle(wl, periodic, prec, device):
     import torch
     B = _B()

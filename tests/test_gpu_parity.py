@@ -84,7 +84,7 @@ def test_dyson_full_matches_dense_oracle(wl, block, device):
 @pytest.mark.parametrize("n_real,n_imag", [(20, 8), (30, 12), (40, 10), (50, 20), (70, 16),
                                            (80, 30), (100, 20), (110, 20), (120, 16)],
                          ids=lambda v: str(v))
-@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("prec", [0, 1, 2], ids=["fp64", "mixed", "bf16x3"])
 def test_tile_counts_match_dense_oracle(n_real, n_imag, prec, device):
     wl = W.custom(2, 2, n_real, n_imag, J0=0.1, seed=n_real)
     c, S_ref, G = oracle_dense(wl)
@@ -185,18 +185,20 @@ def test_config3_block_fp64_sampled_columns(device):
     assert out["stats"]["n_blocks"] == 1
 
 
-# Mixed precision: FP32-MFMA correction sweeps with FP64 residual refinement.
-# Bar (the mixed path's): densities within 1e-8 of the FP64 oracle; at tol=1e-13
-# the refined G itself is checked to 1e-10 relative.
+# Mixed precision: FP32-MFMA (prec 1) or BF16x3 split-product (prec 2) correction
+# sweeps with FP64 residual refinement.  Bar (the mixed path's): densities within
+# 1e-8 of the FP64 oracle; at tol=1e-13 the refined G itself is checked to 1e-10
+# relative.
 @pytest.mark.parametrize("wl,block", [
     (W.config(1), 16),
     (W.custom(3, 5, 7, 5, J0=0.08, seed=4), 4),
     (W.custom(4, 3, 6, 4, J0=0.1, periodic=True, seed=6), 5),
 ], ids=["cfg1", "ragged3x5", "periodic4x3"])
-def test_mixed_precision_matches_dense_oracle(wl, block, device):
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_mixed_precision_matches_dense_oracle(wl, block, prec, device):
     c, S_ref, G = oracle_dense(wl)
     sources = list(range(wl.n_r))
-    prob, out, n, ek = _solve(wl, device, sources, block, prec=1)
+    prob, out, n, ek = _solve(wl, device, sources, block, prec=prec)
     cols_ref = dense_columns(G, wl.n_r, c.n_t, sources)
     assert rel_maxnorm(_np(out["G_cols"]), cols_ref) <= 1e-10
     G_loc = O.local_blocks_from_dense(G, c.n_t, sources)
@@ -205,8 +207,9 @@ def test_mixed_precision_matches_dense_oracle(wl, block, device):
     assert st["lowp_sweeps"] > st["fp64_sweeps"] >= 2
 
 
-def test_config3_block_mixed_sampled_columns(device):
-    out = _golden_columns_check(3, device, 64, prec=1, g_tol=1e-10, n_tol=1e-8)
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_config3_block_mixed_sampled_columns(prec, device):
+    out = _golden_columns_check(3, device, 64, prec=prec, g_tol=1e-10, n_tol=1e-8)
     st = out["stats"]
     assert st["lowp_sweeps"] > 0
 

@@ -171,9 +171,11 @@ def main():
     n_ref = n.clone()
     tts = {}
     legs = () if args.quick else (("fp64_tol1e-12", B.PREC_FP64, args.tol),
-                             ("fp64_tol1e-9", B.PREC_FP64, 1e-9),
-                             ("mixed_fp32_tol1e-9", B.PREC_FP32, 1e-9),
-                                  ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12))
+                                  ("fp64_tol1e-9", B.PREC_FP64, 1e-9),
+                                  ("mixed_fp32_tol1e-9", B.PREC_FP32, 1e-9),
+                                  ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12),
+                                  ("mixed_bf16x3_tol1e-9", B.PREC_BF16X3, 1e-9),
+                                  ("mixed_bf16x3_tol1e-12", B.PREC_BF16X3, 1e-12))
     for label, prec, tol in legs:
         ws_p = ws if prec == B.PREC_FP64 else torch.empty(
             B.workspace_bytes(prob, len(src), block, prec), dtype=torch.uint8, device=dev)
@@ -190,9 +192,9 @@ def main():
         st_p = r["stats"]
         tts[label] = {"seconds": round(t_p, 4),
                       "max_abs_dn": float((n_p - n_ref).abs().max()),
-                      "fp64_sweeps": st_p["fp64_sweeps"], "fp32_sweeps": st_p["lowp_sweeps"],
+                      "fp64_sweeps": st_p["fp64_sweeps"], "lowp_sweeps": st_p["lowp_sweeps"],
                       "fp64_kernel_ms": round(1e3 * st_p["sweep_kernel_seconds"], 2),
-                      "fp32_kernel_ms": round(1e3 * st_p["lowp_kernel_seconds"], 2),
+                      "lowp_kernel_ms": round(1e3 * st_p["lowp_kernel_seconds"], 2),
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
     if tts:
         rec["time_to_solution"] = tts

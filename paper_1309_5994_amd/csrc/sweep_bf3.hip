@@ -7,18 +7,19 @@
 // of Henry, Tang and Heinecke (ARITH 2019): every FP32 value x is carried as
 // x_hi = bf16(x), x_lo = bf16(x - x_hi), and a real product as
 // a_hi b_hi + a_hi b_lo + a_lo b_hi with FP32 accumulation (relative error
-// near 2^-16 per product).  Complex products use the three-product form
-// P1 = ar br, P2 = ai bi, P3 = (ar + ai)(br + bi); re = P1 - P2,
-// im = P3 - P1 - P2, so one complex block product is 9 MFMAs
-// V_MFMA_F32_16X16X32_BF16.
+// near 2^-16 per product).  Complex products use the four-product form
+// re += ar br + ai (-bi), im += ar bi + ai br, so one complex block product
+// is 12 MFMAs V_MFMA_F32_16X16X32_BF16.  (The three-product form saves MFMAs
+// but needs six operand planes per row tile instead of four; the kernel is
+// bound by those LDS fragment reads, not by the matrix cores.)
 //
 // Operands:
 //  * the site operand is precomputed once per solve (launch_bf3_operand):
-//    per site six bf16 planes (hi/lo of ar, ai, ar + ai) of St_i^T, i.e.
+//    per site four bf16 planes (hi/lo of ar, ai) of St_i^T, i.e.
 //    [plane][row a][k], k contiguous and padded with zeros to a multiple of
 //    32, so that a lane's eight consecutive k of one row are 16 bytes;
-//  * the neighbour sum is split into the matching six planes
-//    [plane][column][k] while it is staged.
+//  * the neighbour sum is split into six planes (hi/lo of br, bi, -bi),
+//    [plane][column][k], while it is staged.
 //
 // Work decomposition: as the FP32/FP64 sweeps (one workgroup = one target
 // site and a 32-column tile, 4 waves: two row groups x two 16-column slices,
@@ -37,7 +38,8 @@ namespace {
 constexpr int kThreadsB = 256;
 constexpr int kKB = 32;                  // contour points per chunk (one MFMA k-step)
 constexpr int kRowB = kKB;               // LDS row of one plane, in bf16 (64 bytes)
-constexpr int kPlanes = 6;
+constexpr int kPlanesA = 4;              // ar hi, ar lo, ai hi, ai lo
+constexpr int kPlanesB = 6;              // br hi/lo, bi hi/lo, -bi hi/lo
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -70,8 +72,8 @@ __device__ __forceinline__ void bf3_rows(const __bf16* __restrict__ Ai,
     constexpr int NOWN = MT / 2;
     constexpr bool SHARED = (MT % 2) != 0;
     constexpr int NA = NOWN + (SHARED ? 1 : 0);
-    // St chunk: kPlanes x MP rows x 4 units of 16 bytes.
-    constexpr int A_UNITS = kPlanes * MP * 4;
+    // St chunk: kPlanesA x MP rows x 4 units of 16 bytes.
+    constexpr int A_UNITS = kPlanesA * MP * 4;
     constexpr int A_PER = (A_UNITS + kThreadsB - 1) / kThreadsB;
     constexpr int B_ELEMS = kKB * NW;                   // 1024 per chunk
     constexpr int B_PER = B_ELEMS / kThreadsB;          // 4: one column, 4 consecutive k
@@ -87,11 +89,11 @@ __device__ __forceinline__ void bf3_rows(const __bf16* __restrict__ Ai,
     const int t0 = GRP * NOWN;
     const int wave_u = __builtin_amdgcn_readfirstlane(wave);
 
-    fvec4 acc[NA][3];
+    fvec4 acc[NA][2];   // re, im
 #pragma unroll
     for (int t = 0; t < NA; ++t)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[t][q] = fvec4{0, 0, 0, 0};
+        for (int q = 0; q < 2; ++q) acc[t][q] = fvec4{0, 0, 0, 0};
 
     // Neighbour staging: thread -> column bc, contour points 4 bq .. 4 bq + 3.
     const int bc = tid % NW, bq = tid / NW;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void bf3_rows(const __bf16* __restrict__ Ai,
         }
     };
     auto store_b = [&]() __attribute__((always_inline)) {
-        bf16x4 pl[kPlanes];
+        bf16x4 pl[kPlanesB];
 #pragma unroll
         for (int j = 0; j < B_PER; ++j) {
             const fvec2 v = (rb[j][0] + rb[j][1]) + (rb[j][2] + rb[j][3]);
@@ -134,14 +136,13 @@ __device__ __forceinline__ void bf3_rows(const __bf16* __restrict__ Ai,
             split_bf16(v.y, &h, &l);
             pl[2][j] = h;
             pl[3][j] = l;
-            split_bf16(v.x + v.y, &h, &l);
-            pl[4][j] = h;
-            pl[5][j] = l;
+            pl[4][j] = -h;     // rounding is symmetric: split(-x) = -split(x)
+            pl[5][j] = -l;
         }
         // contour points 4 bq .. 4 bq + 3 = half (bq & 1) of unit bq >> 1
         const int slot = ((bq >> 1) ^ ((bc >> 2) & 3)) * 8 + (bq & 1) * 4;
 #pragma unroll
-        for (int p = 0; p < kPlanes; ++p)
+        for (int p = 0; p < kPlanesB; ++p)
             *reinterpret_cast<bf16x4*>(Bsp + ((size_t)p * NW + bc) * kRowB + slot) = pl[p];
     };
 
@@ -162,35 +163,38 @@ __device__ __forceinline__ void bf3_rows(const __bf16* __restrict__ Ai,
         // rows / columns of a fragment are 16-aligned, so their swizzle is
         // that of l16
         const int fslot = 8 * (lq ^ ((l16 >> 2) & 3));
-        bf16x8 b[kPlanes];
+        bf16x8 b[kPlanesB];
 #pragma unroll
-        for (int p = 0; p < kPlanes; ++p)
+        for (int p = 0; p < kPlanesB; ++p)
             b[p] = *reinterpret_cast<const bf16x8*>(
                 Bsp + ((size_t)p * NW + wc * 16 + l16) * kRowB + fslot);
 #pragma unroll
         for (int t = 0; t < NA; ++t) {
             if (t < nt) {
                 const int tt = t < NOWN ? t0 + t : MT - 1;
-                bf16x8 a[kPlanes];
+                bf16x8 a[kPlanesA];
 #pragma unroll
-                for (int p = 0; p < kPlanes; ++p)
+                for (int p = 0; p < kPlanesA; ++p)
                     a[p] = *reinterpret_cast<const bf16x8*>(
                         As + ((size_t)p * MP + tt * kTile + l16) * kRowB + fslot);
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    acc[t][q] = mma_bf16(a[2 * q + 1], b[2 * q], acc[t][q]);
-                    acc[t][q] = mma_bf16(a[2 * q], b[2 * q + 1], acc[t][q]);
-                    acc[t][q] = mma_bf16(a[2 * q], b[2 * q], acc[t][q]);
-                }
+                // x y ~ x_lo y_hi + x_hi y_lo + x_hi y_hi, small terms first;
+                // plane 2q is hi, 2q + 1 lo.
+#define SCD_X3(acc_, ia, ib)                                                       \
+    acc_ = mma_bf16(a[(ia) + 1], b[(ib)], acc_);                                   \
+    acc_ = mma_bf16(a[(ia)], b[(ib) + 1], acc_);                                   \
+    acc_ = mma_bf16(a[(ia)], b[(ib)], acc_)
+                SCD_X3(acc[t][0], 0, 0);   // re += ar br
+                SCD_X3(acc[t][0], 2, 4);   // re += ai (-bi)
+                SCD_X3(acc[t][1], 0, 2);   // im += ar bi
+                SCD_X3(acc[t][1], 2, 0);   // im += ai br
+#undef SCD_X3
             }
         }
     }
 
     // Complex partial sums of tile t, element v.
-    auto part_re = [&](int t, int v) -> float { return acc[t][0][v] - acc[t][1][v]; };
-    auto part_im = [&](int t, int v) -> float {
-        return acc[t][2][v] - acc[t][0][v] - acc[t][1][v];
-    };
+    auto part_re = [&](int t, int v) -> float { return acc[t][0][v]; };
+    auto part_im = [&](int t, int v) -> float { return acc[t][1][v]; };
 
     // Shared tile: group 1 hands its partial sums to group 0 through LDS.
     float sh_re[4] = {0, 0, 0, 0}, sh_im[4] = {0, 0, 0, 0};
@@ -270,11 +274,11 @@ void bf3_kernel(const __bf16* __restrict__ Abf, const int* __restrict__ src_blk,
     constexpr int MP = kTile * MT;
     constexpr int KP = bf3_kpad(MT);
     constexpr int NW = kColsPerWG;
-    constexpr int A_UNITS = kPlanes * MP * 4;
+    constexpr int A_UNITS = kPlanesA * MP * 4;
     constexpr int A_BYTES = (A_UNITS + kThreadsB - 1) / kThreadsB * kThreadsB * 16;
     static_assert(A_BYTES >= 2 * 4 * 2 * 64 * 4, "As also carries the shared tile's sums");
     __shared__ __attribute__((aligned(16))) __bf16 As[A_BYTES / 2];
-    __shared__ __attribute__((aligned(16))) __bf16 Bsp[kPlanes * NW * kRowB];
+    __shared__ __attribute__((aligned(16))) __bf16 Bsp[kPlanesB * NW * kRowB];
     __shared__ double red[kThreadsB / 64][3];
 
     const int tid = threadIdx.x;
@@ -312,7 +316,7 @@ void bf3_kernel(const __bf16* __restrict__ Abf, const int* __restrict__ src_blk,
 
     int nb[4];
     site_neighbours(i, g.Lx, g.Ly, g.periodic, nb);
-    const __bf16* Ai = Abf + (size_t)i * kPlanes * MP * KP;
+    const __bf16* Ai = Abf + (size_t)i * kPlanesA * MP * KP;
     const fvec2* Xk[4];
     for (int d = 0; d < 4; ++d) Xk[d] = nb[d] >= 0 ? X + (size_t)nb[d] * MP * g.ldx : nullptr;
 
@@ -323,8 +327,9 @@ void bf3_kernel(const __bf16* __restrict__ Abf, const int* __restrict__ src_blk,
         bf3_rows<MT, 1>(Ai, Xk, src_blk, X, out, R, part, g, i, n0, As, Bsp, red);
 }
 
-// Six bf16 planes per site from St (complex128 [site][c][a], mp x mp):
-// plane[p][a][k] for k < mp (St_i[k][a] split), zero for mp <= k < kp.
+// Four bf16 planes per site from St (complex128 [site][c][a], mp x mp):
+// plane[p][a][k] for k < mp (hi/lo of Re and Im of St_i[k][a]), zero for
+// mp <= k < kp.
 __global__ __launch_bounds__(256)
 void bf3_operand_kernel(const dvec2* __restrict__ St, int n_sites, int mp, int kp,
                         __bf16* __restrict__ out) {
@@ -334,14 +339,13 @@ void bf3_operand_kernel(const dvec2* __restrict__ St, int n_sites, int mp, int k
          e += (size_t)gridDim.x * blockDim.x) {
         const size_t site = e / per, rem = e - site * per;
         const int a = (int)(rem / kp), k = (int)(rem - (size_t)a * kp);
-        float xr = 0.0f, xi = 0.0f, xs = 0.0f;
+        float xr = 0.0f, xi = 0.0f;
         if (k < mp) {
             const dvec2 v = St[(site * mp + k) * mp + a];
             xr = (float)v.x;
             xi = (float)v.y;
-            xs = (float)(v.x + v.y);
         }
-        __bf16* o = out + site * kPlanes * per + rem;
+        __bf16* o = out + site * kPlanesA * per + rem;
         __bf16 h, l;
         split_bf16(xr, &h, &l);
         o[0 * per] = h;
@@ -349,16 +353,13 @@ void bf3_operand_kernel(const dvec2* __restrict__ St, int n_sites, int mp, int k
         split_bf16(xi, &h, &l);
         o[2 * per] = h;
         o[3 * per] = l;
-        split_bf16(xs, &h, &l);
-        o[4 * per] = h;
-        o[5 * per] = l;
     }
 }
 
 }  // namespace
 
 size_t bf3_operand_bytes(const Geom& g) {
-    return (size_t)g.n_r * kPlanes * g.mp * bf3_kpad(g.mt) * sizeof(__bf16);
+    return (size_t)g.n_r * kPlanesA * g.mp * bf3_kpad(g.mt) * sizeof(__bf16);
 }
 
 hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipStream_t st) {

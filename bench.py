@@ -25,7 +25,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (MFMA = vector)
 # The sweep kernel and the host code that orders its tiles (the site order
 # decides how much of the traffic the caches absorb).
 TRAFFIC_SOURCES = [os.path.join(ROOT, "paper_1309_5994_amd", "csrc", f)
-                   for f in ("sweep.hip", "api.hip")]
+                   for f in ("sweep.hip", "order.hip")]
 PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_fp64_trap16x16_nt144.md")
 
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "scdyson.h"
 
@@ -102,6 +103,15 @@ __device__ inline int xcd_remap(int bid, int nb) {
     if (bid >= (per << 3)) return bid;
     return (bid & 7) * per + (bid >> 3);
 }
+
+// ---- tile order (order.hip) ----
+// Sites per tile-order group (SCD_SITE_GROUP overrides the default).
+int site_group(const Geom& g);
+// Square lattice patches of the colour order (SCD_PATCH overrides).
+int colour_patch(const Geom& g);
+// Launch site list: the two colours of a bipartite lattice (*n_even = size of
+// the first) or all sites, each interleaved over the XCDs in groups.
+std::vector<int32_t> colour_order(const Geom& g, int group, bool bipartite, int* n_even);
 
 // ---- launchers (each returns hipError_t of the launch) ----
 hipError_t launch_sigma_build(const Geom& g, const double* V, const double* U, double2* S,

@@ -30,9 +30,9 @@ def test_workspace_bytes_layout():
     assert B.workspace_bytes(q, 12, 12) >= 12 * 64 * 64 * 16 + 2 * 12 * 64 * 608 * 16
     # FP32 refinement: + complex64 operand, residual and correction
     assert B.workspace_bytes(p, 16, 16, 1) >= n + 16 * 64 * 64 * 8 + 2 * 16 * 64 * 800 * 8
-    # BF16x3 refinement: six bf16 planes of the operand (K padded to 64) instead
-    # of the complex64 one
-    assert B.workspace_bytes(p, 16, 16, 2) >= n + 16 * 6 * 64 * 64 * 2 + 2 * 16 * 64 * 800 * 8
+    # BF16x3 refinement: four bf16 planes of the operand (hi/lo of Re and Im, K
+    # padded to 64) instead of the complex64 one
+    assert B.workspace_bytes(p, 16, 16, 2) >= n + 16 * 4 * 64 * 64 * 2 + 2 * 16 * 64 * 800 * 8
 
 
 @pytest.mark.parametrize("kw,msg", [

@@ -88,6 +88,31 @@ def cpu_baseline(wl, flops_per_source):
             "seconds": secs}
 
 
+def adjoint_leg(B, prob, S, V, U, J, wl, forward_full_s):
+    """Wall time of the density loss L = sum_i w_i n_i(t_end) and of its
+    gradients (dyson_adjoint, FP64, tol 1e-12): the forward columns alone, and
+    forward + transposed solve + gradient kernels; each also as a multiple of
+    the full-G FP64 step timed above."""
+    import torch
+    w = torch.tensor(W.loss_weights(wl.n_r), dtype=torch.float64, device=S.device)
+    ws = torch.empty(B.adjoint_workspace_bytes(prob, B.PREC_FP64), dtype=torch.uint8,
+                     device=S.device)
+    out = {}
+    for label, grads in (("loss_only", False), ("loss_and_grads", True)):
+        for rep in range(2):          # first repetition warms up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = B.dyson_adjoint(prob, S, V, U, J, w=w, prec=B.PREC_FP64, tol=1e-12, grads=grads,
+                                ws=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+        out[label] = {"seconds": round(dt, 4), "x_full_forward": round(dt / forward_full_s, 4),
+                      "sweeps": r["stats"]["sweeps_total"]}
+    out["grads_over_loss"] = round(out["loss_and_grads"]["seconds"] /
+                                   out["loss_only"]["seconds"], 3)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -198,6 +223,8 @@ def main():
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
     if tts:
         rec["time_to_solution"] = tts
+    if not args.quick:
+        rec["adjoint"] = adjoint_leg(B, prob, S, V, U, J, wl, rec["time_to_solution_s"])
     if not args.no_cpu:
         per_source = stats[-1]["gemm_flops"] / len(src)
         rec["cpu_baseline"] = cpu_baseline(wl, per_source)

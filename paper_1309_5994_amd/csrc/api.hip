@@ -357,6 +357,7 @@ struct Solver {
         const int cps = a.x0_kind == X0_BLOCK ? g.n_t : 1;
         const size_t n_elem = (size_t)g.n_r * g.mp * a.ldx;
         const size_t bytes32 = n_elem * sizeof(float2);
+        // R and D0 start at zero: tiles beyond the light cone are never written.
         SCD_HIP(hipMemsetAsync(R32, 0, bytes32, st), "clear");
         SCD_HIP(hipMemsetAsync(D0, 0, bytes32, st), "clear");
         if (D1) SCD_HIP(hipMemsetAsync(D1, 0, bytes32, st), "clear");
@@ -372,8 +373,13 @@ struct Solver {
             a.check = 1;
             a.lc_sweep = cone ? radius_x : -1;
             SCD_HIP(t64.mark(st), "event record");
+            // The residual kernel also writes R into D0, the correction's start
+            // (D_0 = R): outside its light cone both stay zero, as D0 was never
+            // written there by earlier correction sweeps (their cone is smaller).
+            a.out2 = D0;
             SCD_HIP(launch_residual_f64(g, a, St, S, src_blk, X, R32, partial, st),
                     "residual launch");
+            a.out2 = nullptr;
             SCD_HIP(t64.mark(st), "event record");
             double r[3];
             if (reduce(r)) return SCD_EHIP;
@@ -406,7 +412,6 @@ struct Solver {
             const double inner_tol =
                 std::min(0.1, std::max(floor, 0.3 * tol * (1.0 - rho_g) / e_r));
             const int radius_r = radius_x + 1;
-            SCD_HIP(launch_copy_f32(R32, D0, n_elem, st), "copy launch");
             void* dc = D0;
             void* dn = D1;
             double e_prev = 0.0;

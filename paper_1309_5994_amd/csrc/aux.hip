@@ -187,17 +187,24 @@ void to_f32_kernel(const dvec2* __restrict__ in, fvec2* __restrict__ out, size_t
     }
 }
 
-__global__ __launch_bounds__(256)
-void copy_f32_kernel(const fvec2* __restrict__ in, fvec2* __restrict__ out, size_t n) {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (size_t)gridDim.x * blockDim.x)
-        out[e] = in[e];
-}
-
-// X += D: the FP64 iterate absorbs the low-precision correction.
+// X += D: the FP64 iterate absorbs the low-precision correction; four
+// elements per thread and step (16-byte accesses, more bytes in flight).
 __global__ __launch_bounds__(256)
 void axpy_kernel(dvec2* __restrict__ X, const fvec2* __restrict__ D, size_t n) {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+    const size_t n4 = n / 4;
+    const fvec4* D4 = reinterpret_cast<const fvec4*>(D);
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const fvec4 d0 = D4[2 * e], d1 = D4[2 * e + 1];
+        dvec2* x = X + 4 * e;
+        const dvec2 x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
+        x[0] = x0 + dvec2{(double)d0.x, (double)d0.y};
+        x[1] = x1 + dvec2{(double)d0.z, (double)d0.w};
+        x[2] = x2 + dvec2{(double)d1.x, (double)d1.y};
+        x[3] = x3 + dvec2{(double)d1.z, (double)d1.w};
+    }
+    // tail (n not a multiple of 4)
+    for (size_t e = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (size_t)gridDim.x * blockDim.x) {
         const fvec2 d = D[e];
         X[e] += dvec2{(double)d.x, (double)d.y};
@@ -209,12 +216,6 @@ void axpy_kernel(dvec2* __restrict__ X, const fvec2* __restrict__ D, size_t n) {
 hipError_t launch_to_f32(const double2* in, void* out, size_t n, hipStream_t st) {
     hipLaunchKernelGGL(to_f32_kernel, dim3(4096), dim3(256), 0, st,
                        reinterpret_cast<const dvec2*>(in), reinterpret_cast<fvec2*>(out), n);
-    return hipGetLastError();
-}
-
-hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st) {
-    hipLaunchKernelGGL(copy_f32_kernel, dim3(4096), dim3(256), 0, st,
-                       reinterpret_cast<const fvec2*>(in), reinterpret_cast<fvec2*>(out), n);
     return hipGetLastError();
 }
 

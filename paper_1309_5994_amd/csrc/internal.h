@@ -49,6 +49,8 @@ struct SweepArgs {
     int n_sites;    // number of updated sites
     int part_off;   // offset (in workgroups) of this launch's convergence partials
     int check;      // 1: read old values and reduce the increment; 0: write only
+    void* out2 = nullptr;  // RESIDUAL: second destination of R (the start of the
+                           // correction sweeps), or nullptr
 };
 
 // X0 of a column block (the preconditioned unit-vector bundle):
@@ -138,7 +140,6 @@ hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipSt
 hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st);
-hipError_t launch_copy_f32(const void* in, void* out, size_t n, hipStream_t st);
 hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st);
 hipError_t launch_adjoint_grads(const Geom& g, int ldx, int e, const double2* H, const double2* Gc,
                                 const double* V, const double* U, const double* J, const double* w,

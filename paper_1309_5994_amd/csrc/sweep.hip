@@ -368,6 +368,9 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                     reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{re, im};
                 } else {
                     reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
+                    if (g.out2)
+                        reinterpret_cast<fvec2*>(g.out2)[site_off + off] =
+                            fvec2{(float)dr, (float)di};
                 }
                 if (need_old) mdiff = fmax(mdiff, fmax(fabs(dr), fabs(di)));
                 mabs = fmax(mabs, fmax(fabs(re), fabs(im)));

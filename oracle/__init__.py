@@ -23,6 +23,8 @@ What it computes (plain, slow, obviously correct, complex128 throughout):
                      lowest order), selected columns by exact block-tridiagonal
                      elimination in lattice rows, and Neumann partial sums
                      (App. C, the Dyson-series view).
+* ``gmres``       -- preconditioned restarted GMRES per unit-vector column
+                     (App. C), the paper's own solver for the same system.
 * ``observables`` -- occupancy and kinetic energy (Sec. III.A).
 * ``gradients``   -- dense adjoint formulas for d(sum_i w_i n_i(t_end)).
 
@@ -38,6 +40,7 @@ from .atomic import atomic_gf, atomic_gf_fock, boltzmann_weights, level_phases
 from .lattice import neighbours, hopping_on_contour, hopping_operator_dense
 from .dyson import (blockdiag, dyson_dense, dyson_columns_blocktri,
                     neumann_partial_sums, dense_system_matrix)
+from .gmres import gmres_column, gmres_dense
 from .observables import occupancy, kinetic_energy
 from .gradients import (loss_and_grad_dense, loss_dense, site_levels,
                         atomic_gf_derivatives)
@@ -48,7 +51,7 @@ __all__ = [
     "atomic_gf", "atomic_gf_fock", "boltzmann_weights", "level_phases",
     "neighbours", "hopping_on_contour", "hopping_operator_dense",
     "blockdiag", "dyson_dense", "dyson_columns_blocktri",
-    "neumann_partial_sums", "dense_system_matrix",
+    "neumann_partial_sums", "dense_system_matrix", "gmres_column", "gmres_dense",
     "occupancy", "kinetic_energy", "loss_and_grad_dense", "loss_dense",
     "site_levels", "atomic_gf_derivatives",
     "local_blocks_from_dense", "neighbour_blocks_from_dense",

@@ -92,6 +92,13 @@ typedef struct scd_stats {
     double  lowp_kernel_seconds;  /* summed HIP-event time of the FP32 correction sweeps */
     int32_t sweep_launches; /* FP64 sweep-kernel launches timed                 */
     int32_t lowp_launches;  /* FP32 correction-sweep launches timed             */
+    double  stream_kernel_seconds; /* dyson_gmres: summed HIP-event time of the
+                               streaming kernels (Gram-Schmidt passes, Givens
+                               rotations, solution update)                      */
+    double  stream_bytes;   /* dyson_gmres: algorithmic HBM bytes those kernels move
+                               (every Krylov vector read or written once per pass) */
+    int32_t stream_launches;/* dyson_gmres: streaming-kernel launches timed     */
+    int32_t reserved;       /* zero                                             */
 } scd_stats;
 
 /*
@@ -147,6 +154,44 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J,
                   int32_t prec, double tol, int32_t max_iter,
                   void* G_cols, void* G_loc, void* G_nn,
                   void* ws, size_t ws_bytes, scd_stats* st, void* stream);
+
+/*
+ * Device workspace (bytes) that dyson_gmres needs for n_src source sites in
+ * column blocks of block_sites sources with `restart` Krylov vectors per cycle.
+ * Returns SCD_OK and writes *bytes, or SCD_EINVAL.
+ */
+int scd_gmres_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites,
+                              int32_t restart, size_t* bytes);
+
+/*
+ * Solve G = S + S D G for the columns of the listed source sites by
+ * preconditioned restarted GMRES (App. C), the solver the paper uses.  Every
+ * column (s, b) of a block is the unit-vector system A x = e of
+ * eq. blockedGMRESproblem with A = B - J (eq. Ginvblockstruct) and the
+ * block-diagonal preconditioner P = B^-1 = S (eq. definitionB, lowest order):
+ *     (I - S D) u = S e,   start u0 = S e,
+ * and GMRES(restart) minimises each column's preconditioned residual
+ * |S e - (I - S D) u|_2 over u0 + K_d(I - S D, z0).  All columns of a block
+ * advance in lock step: one batched matvec per Arnoldi step (the fused
+ * stencil + contour GEMM of the sweeps), then per-column Gram-Schmidt
+ * (classical, applied twice), Hessenberg column and Givens rotation.  It
+ * converges also where the Dyson series diverges (spectral radius of S D >= 1).
+ *   restart    Krylov vectors per cycle, 1..16; the workspace holds restart + 2
+ *              iterates of a block (size block_sites to fit HBM)
+ *   tol        stop when every column's preconditioned residual 2-norm is at most
+ *              tol times the 2-norm of its S e (checked after every Arnoldi step
+ *              through the rotated Hessenberg system)
+ *   max_iter   Arnoldi steps (batched matvecs) per block
+ *   other arguments as dyson_iterate; FP64 throughout.
+ * st: sweeps_total / sweeps_max count Arnoldi steps; fp64_sweeps every batched
+ * matvec including the residual recomputed at each (re)start; final_err the
+ * largest relative residual; rho_est the mean residual reduction per step.
+ * Errors as dyson_iterate (GMRES residuals never grow, so no SCD_EDIVERGED).
+ */
+int dyson_gmres(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                int32_t n_src, int32_t block_sites, int32_t restart, double tol,
+                int32_t max_iter, void* G_cols, void* G_loc, void* G_nn, void* ws,
+                size_t ws_bytes, scd_stats* st, void* stream);
 
 /*
  * Local observables of Sec. III.A from the blocks dyson_iterate returns.

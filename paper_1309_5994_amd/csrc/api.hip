@@ -187,6 +187,23 @@ struct CheckPlan {
     }
 };
 
+// Device buffers of the batched GMRES of one column block (see gm_layout).
+struct GmBufs {
+    double2* u;          // iterate
+    double2* Q;          // basis v_0 .. v_restart, qstride elements apart
+    size_t qstride;
+    double2 *pa, *pb;    // Gram-Schmidt dot partials [nch][kMaxBasis][ldx]
+    double* pn;          // norm partials [nch][ldx]
+    double* sig;         // [kMaxBasis + 1][ldx]
+    double2* R;          // [kMaxBasis][kMaxBasis][ldx]
+    double* cs;          // [kMaxBasis][ldx]
+    double2* sn;         // [kMaxBasis][ldx]
+    double2* gv;         // [kMaxBasis + 1][ldx]
+    double2* y;          // [kMaxBasis][ldx]
+    double* x0n;         // [ldx]
+    int rows, ldx, nch;
+};
+
 // Host side of the sweep loops of one column block.
 struct Solver {
     Geom g;
@@ -202,7 +219,7 @@ struct Solver {
     const int* colour_sites[2] = {nullptr, nullptr};   // device site lists (red-black)
     int n_colour[2] = {0, 0};
     const int* all_sites = nullptr;   // device list of all n_r sites (launches over every site)
-    LaunchTimer t64, t32;
+    LaunchTimer t64, t32, ts;         // FP64 sweeps, low-precision sweeps, streaming passes
     std::vector<double> within[3];   // (target, source) pairs within distance d, cumulative:
                                      // [0] all targets, [1] even-colour, [2] odd-colour targets
 
@@ -235,18 +252,21 @@ struct Solver {
     }
     // Fold the per-workgroup partials of the last sweep and collect the launch
     // timings; returns SCD_OK or SCD_EHIP.
-    int reduce(double out[3]) {
+    int reduce(double out[3], int n_parts = 0) {
         SCD_HIP(hipMemsetAsync(slot, 0, 4 * sizeof(unsigned long long), st), "slot clear");
-        SCD_HIP(launch_reduce_max3(partial, nwg, slot, st), "reduce launch");
+        SCD_HIP(launch_reduce_max3(partial, n_parts > 0 ? n_parts : nwg, slot, st),
+                "reduce launch");
         unsigned long long h[3];
         SCD_HIP(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st), "slot copy");
         SCD_HIP(hipStreamSynchronize(st), "sweep sync");
         for (int q = 0; q < 3; ++q) out[q] = bits_to_double(h[q]);
-        double s64 = 0.0, s32 = 0.0;
+        double s64 = 0.0, s32 = 0.0, sst = 0.0;
         SCD_HIP(t64.drain(&s64), "event time");
         SCD_HIP(t32.drain(&s32), "event time");
+        SCD_HIP(ts.drain(&sst), "event time");
         stats->sweep_kernel_seconds += s64;
         stats->lowp_kernel_seconds += s32;
+        stats->stream_kernel_seconds += sst;
         return SCD_OK;
     }
     bool red_black() const { return colour_sites[0] != nullptr; }
@@ -447,6 +467,179 @@ struct Solver {
         res->rho = rho;
         return code;
     }
+
+    // One streaming pass, timed and counted; `vectors` = Krylov-sized vectors
+    // it reads plus writes.
+    int gs(int mode, GsPass p, int vectors) {
+        SCD_HIP(ts.mark(st), "event record");
+        SCD_HIP(launch_gs(mode, p, st), "Gram-Schmidt launch");
+        SCD_HIP(ts.mark(st), "event record");
+        stats->stream_launches++;
+        stats->stream_bytes += (double)vectors * p.rows * (double)p.ldx * sizeof(double2);
+        return SCD_OK;
+    }
+
+    // Batched GMRES(restart) of one column block (App. C), all columns in lock
+    // step from u = X0: at each (re)start the FP64 residual z = X0 + St^T N(u) - u
+    // (the preconditioned residual S e - (I - S D) u) becomes v_0; each Arnoldi
+    // step is one batched matvec w = St^T N(v_d) (sweep kernel without X0)
+    // followed by classical Gram-Schmidt applied twice and the Givens update of
+    // every column's Hessenberg system.  Stops when the largest relative
+    // residual |g_{d+1}| / |X0| over the columns is at most tol.
+    int solve_gmres(SweepArgs a, const int* src_blk, const GmBufs& b, int restart, double tol,
+                    int max_iter, BlockResult* res) {
+        const int cps = g.n_t;
+        const bool cone = a.lc_sweep >= 0;
+        const size_t vbytes = (size_t)b.rows * b.ldx * sizeof(double2);
+        const int ngw = (b.ldx + 255) / 256;
+        GsPass p{};
+        p.Q = b.Q;
+        p.qstride = b.qstride;
+        p.sig = b.sig;
+        p.rows = b.rows;
+        p.ldx = b.ldx;
+        p.chunk_rows = (b.rows + b.nch - 1) / b.nch;
+        p.pnorm = b.pn;
+        const size_t pstride = (size_t)kMaxBasis * b.ldx;
+        GivensArgs ga{};
+        ga.pa = b.pa;
+        ga.pb = b.pb;
+        ga.pn = b.pn;
+        ga.nch = b.nch;
+        ga.ldx = b.ldx;
+        ga.sig = b.sig;
+        ga.R = b.R;
+        ga.cs = b.cs;
+        ga.sn = b.sn;
+        ga.gv = b.gv;
+        ga.x0n = b.x0n;
+        ga.part = partial;
+
+        // |X0| per column (u = X0 on entry).
+        {
+            GsPass q = p;
+            q.k = 0;
+            q.w = b.u;
+            if (gs(GS_NORM, q, 1)) return SCD_EHIP;
+            SCD_HIP(launch_colnorm(b.pn, b.nch, b.ldx, b.x0n, st), "column norm launch");
+        }
+        int radius_u = 0, n = 0, cleared = 0, code = SCD_ENOTCONV;
+        double e = 0.0, e0 = 0.0;
+        double r[3];
+        auto clear_basis = [&](int j) -> int {
+            // Tiles beyond the light cone are never written by the matvec.
+            if (j < cleared) return SCD_OK;
+            SCD_HIP(hipMemsetAsync(b.Q + (size_t)j * b.qstride, 0, vbytes, st), "basis clear");
+            cleared = j + 1;
+            return SCD_OK;
+        };
+        for (;;) {
+            // (Re)start: v_0 = z = X0 + St^T N(u) - u, sig_0 = 1 / |z| per column.
+            if (clear_basis(0)) return SCD_EHIP;
+            a.sites = all_sites;
+            a.n_sites = g.n_r;
+            a.part_off = 0;
+            a.check = 1;
+            a.no_x0 = 0;
+            a.out_f64 = 1;
+            a.lc_sweep = cone ? radius_u : -1;
+            SCD_HIP(t64.mark(st), "event record");
+            SCD_HIP(launch_residual_f64(g, a, St, S, src_blk, b.u, b.Q, partial, st),
+                    "residual launch");
+            SCD_HIP(t64.mark(st), "event record");
+            a.out_f64 = 0;
+            stats->fp64_sweeps++;
+            stats->sweep_launches++;
+            stats->gemm_flops += sweep_flops(cone ? radius_u + 1 : 1 << 20, cps);
+            {
+                GsPass q = p;
+                q.k = 0;
+                q.w = b.Q;
+                if (gs(GS_NORM, q, 1)) return SCD_EHIP;
+            }
+            ga.d = -1;
+            SCD_HIP(launch_givens(ga, st), "Givens launch");
+            if (reduce(r, ngw)) return SCD_EHIP;
+            if (r[2] != 0.0 || !std::isfinite(r[0])) {
+                code = fail(SCD_ENAN, "NaN or Inf in the GMRES residual after %d steps", n);
+                break;
+            }
+            e = r[0];
+            if (n == 0) e0 = e;
+            if (e <= tol) {
+                code = SCD_OK;
+                break;
+            }
+            if (n >= max_iter) break;
+            for (int d = 0; d < restart; ++d) {
+                double2* v = b.Q + (size_t)d * b.qstride;
+                double2* w = b.Q + (size_t)(d + 1) * b.qstride;
+                if (clear_basis(d + 1)) return SCD_EHIP;
+                // w = St^T N(v_d): the operator applied to the unscaled v_d.
+                a.no_x0 = 1;
+                a.check = 0;
+                a.lc_sweep = cone ? radius_u + 1 + d : -1;
+                SCD_HIP(t64.mark(st), "event record");
+                SCD_HIP(launch_sweep_f64(g, a, St, S, src_blk, v, w, partial, st),
+                        "matvec launch");
+                SCD_HIP(t64.mark(st), "event record");
+                a.no_x0 = 0;
+                stats->fp64_sweeps++;
+                stats->sweep_launches++;
+                stats->gemm_flops += sweep_flops(cone ? radius_u + 2 + d : 1 << 20, cps);
+                const int k = d + 1;
+                GsPass q = p;
+                q.k = k;
+                q.w = w;
+                q.wsig = b.sig + (size_t)d * b.ldx;     // T q_d = sig_d T v_d
+                q.pdot = b.pa;
+                if (gs(GS_DOTS, q, k + 1)) return SCD_EHIP;
+                q.coef = b.pa;
+                q.coef_parts = b.nch;
+                q.coef_pstride = pstride;
+                q.pdot = b.pb;
+                if (gs(GS_UPDATE_DOTS, q, k + 2)) return SCD_EHIP;
+                q.wsig = nullptr;
+                q.coef = b.pb;
+                if (gs(GS_UPDATE_NORM, q, k + 2)) return SCD_EHIP;
+                ga.d = d;
+                SCD_HIP(ts.mark(st), "event record");
+                SCD_HIP(launch_givens(ga, st), "Givens launch");
+                SCD_HIP(ts.mark(st), "event record");
+                ++n;
+                if (reduce(r, ngw)) return SCD_EHIP;
+                if (r[2] != 0.0 || !std::isfinite(r[0])) {
+                    code = fail(SCD_ENAN, "NaN or Inf in the GMRES residual at step %d", n);
+                    break;
+                }
+                e = r[0];
+                if (e <= tol) code = SCD_OK;
+                if (code == SCD_OK || n >= max_iter || d == restart - 1) {
+                    // u += sum_i y_i q_i over the k basis vectors of this cycle.
+                    SCD_HIP(ts.mark(st), "event record");
+                    SCD_HIP(launch_gmres_solve(b.R, b.gv, b.y, k, b.ldx, st), "solve launch");
+                    SCD_HIP(ts.mark(st), "event record");
+                    GsPass uq = p;
+                    uq.k = k;
+                    uq.w = b.u;
+                    uq.coef = b.y;
+                    uq.coef_parts = 1;
+                    uq.coef_pstride = 0;
+                    if (gs(GS_UPDATE, uq, k + 2)) return SCD_EHIP;
+                    radius_u += 1 + d;
+                    break;
+                }
+            }
+            if (code != SCD_ENOTCONV || n >= max_iter) break;
+        }
+        double tail[3];
+        if (reduce(tail, ngw)) return SCD_EHIP;     // drains the last timings
+        res->X = b.u;
+        res->sweeps = n;
+        res->err = e;
+        res->rho = (n > 0 && e0 > 0.0 && e > 0.0) ? std::pow(e / e0, 1.0 / n) : 0.0;
+        return code;
+    }
 };
 
 }  // namespace
@@ -614,6 +807,203 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         if (res.sweeps > stats.sweeps_max) stats.sweeps_max = res.sweeps;
         worst_err = res.err > worst_err ? res.err : worst_err;
         worst_rho = res.rho > worst_rho ? res.rho : worst_rho;
+        SCD_HIP(launch_extract(g, res.X, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
+                               (double2*)G_loc, (double2*)G_nn, st),
+                "extract launch");
+        if (code != SCD_OK) {
+            final_code = code;
+            break;
+        }
+    }
+    SCD_HIP(hipStreamSynchronize(st), "final sync");
+    stats.final_err = worst_err;
+    stats.rho_est = worst_rho;
+    if (final_code == SCD_OK) g_last_error.clear();
+    return finish(final_code);
+}
+
+// ---- GMRES -----------------------------------------------------------------
+
+namespace {
+
+struct GmLayout {
+    int ldx, ntn, nwg, nch, rows;
+    size_t off_st, off_u, off_q, qstride_bytes, off_pa, off_pb, off_pn, off_sig, off_R, off_cs,
+        off_sn, off_g, off_y, off_x0n, off_partial, off_slot, off_src, off_order, total;
+};
+
+// Workspace of dyson_gmres: St, the iterate u, restart + 1 basis vectors (each
+// an FP64 block iterate), the Gram-Schmidt partials and per-column Hessenberg
+// state (O(kMaxBasis^2) complex per column).
+GmLayout gm_layout(const Geom& g, int n_src, int block_sites, int restart) {
+    GmLayout L;
+    const int bs = block_sites < n_src ? block_sites : n_src;
+    L.ldx = ((bs * g.n_t + kColsPerWG - 1) / kColsPerWG) * kColsPerWG;
+    L.ntn = L.ldx / kColsPerWG;
+    L.nwg = g.n_r * L.ntn;
+    L.rows = g.n_r * g.mp;
+    L.nch = gs_chunks(L.rows, L.ldx);
+    const size_t it64 = (size_t)L.rows * L.ldx * sizeof(double2);
+    const size_t col = (size_t)L.ldx;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    L.off_st = take((size_t)g.n_r * g.mp * g.mp * sizeof(double2));
+    L.off_u = take(it64);
+    L.qstride_bytes = align256(it64);
+    L.off_q = take(L.qstride_bytes * (size_t)(restart + 1));
+    L.off_pa = take((size_t)L.nch * kMaxBasis * col * sizeof(double2));
+    L.off_pb = take((size_t)L.nch * kMaxBasis * col * sizeof(double2));
+    L.off_pn = take((size_t)L.nch * col * sizeof(double));
+    L.off_sig = take((size_t)(kMaxBasis + 1) * col * sizeof(double));
+    L.off_R = take((size_t)kMaxBasis * kMaxBasis * col * sizeof(double2));
+    L.off_cs = take((size_t)kMaxBasis * col * sizeof(double));
+    L.off_sn = take((size_t)kMaxBasis * col * sizeof(double2));
+    L.off_g = take((size_t)(kMaxBasis + 1) * col * sizeof(double2));
+    L.off_y = take((size_t)kMaxBasis * col * sizeof(double2));
+    L.off_x0n = take(col * sizeof(double));
+    const size_t nparts = std::max((size_t)L.nwg, (L.ldx + 255) / (size_t)256);
+    L.off_partial = take(nparts * 3 * sizeof(double));
+    L.off_slot = take(4 * sizeof(unsigned long long));
+    L.off_src = take((size_t)n_src * sizeof(int32_t));
+    L.off_order = take((size_t)g.n_r * sizeof(int32_t));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+int scd_gmres_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block_sites,
+                              int32_t restart, size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
+    if (n_src < 1 || n_src > g.n_r) return fail(SCD_EINVAL, "n_src must be in [1, N_r]");
+    if (block_sites < 1) return fail(SCD_EINVAL, "block_sites must be >= 1");
+    if (restart < 1 || restart > kMaxBasis)
+        return fail(SCD_EINVAL, "restart must be in [1, %d]", kMaxBasis);
+    *bytes = gm_layout(g, n_src, block_sites, restart).total;
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int dyson_gmres(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                int32_t n_src, int32_t block_sites, int32_t restart, double tol, int32_t max_iter,
+                void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
+                scd_stats* st_out, void* stream) {
+    const auto t_start = std::chrono::steady_clock::now();
+    scd_stats stats;
+    std::memset(&stats, 0, sizeof stats);
+    auto finish = [&](int code) {
+        stats.status = code;
+        stats.seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+        if (st_out) *st_out = stats;
+        return code;
+    };
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return finish(rc);
+    if (!S || !J || !src || !G_loc || !ws)
+        return finish(fail(SCD_EINVAL, "S, J, src, G_loc and ws must be non-NULL"));
+    if (n_src < 1 || n_src > g.n_r) return finish(fail(SCD_EINVAL, "n_src must be in [1, N_r]"));
+    if (block_sites < 1) return finish(fail(SCD_EINVAL, "block_sites must be >= 1"));
+    if (restart < 1 || restart > kMaxBasis)
+        return finish(fail(SCD_EINVAL, "restart must be in [1, %d]", kMaxBasis));
+    if (!(tol > 0.0) || !std::isfinite(tol)) return finish(fail(SCD_EINVAL, "tol must be > 0"));
+    if (max_iter < 1) return finish(fail(SCD_EINVAL, "max_iter must be >= 1"));
+    for (int s = 0; s < n_src; ++s)
+        if (src[s] < 0 || src[s] >= g.n_r)
+            return finish(fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r));
+    const GmLayout L = gm_layout(g, n_src, block_sites, restart);
+    if (ws_bytes < L.total)
+        return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total));
+
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    Solver sv;
+    sv.g = g;
+    sv.st = st;
+    sv.stats = &stats;
+    sv.St = (double2*)(base + L.off_st);
+    sv.St32 = nullptr;
+    sv.S = (const double2*)S;
+    sv.partial = (double*)(base + L.off_partial);
+    sv.slot = (unsigned long long*)(base + L.off_slot);
+    sv.nwg = L.nwg;
+    int* src_dev = (int*)(base + L.off_src);
+    SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
+            "copy src");
+    int n_even = 0;
+    const std::vector<int32_t> order = colour_order(g, site_group(g), lattice_bipartite(g), &n_even);
+    int* order_dev = (int*)(base + L.off_order);
+    SCD_HIP(hipMemcpyAsync(order_dev, order.data(), (size_t)g.n_r * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
+            "copy site order");
+    sv.all_sites = order_dev;     // every launch is Jacobi-style (all sites)
+    SCD_HIP(launch_scale_transpose(g, (const double2*)S, J, sv.St, 0, st), "scale_transpose launch");
+    SCD_HIP(hipStreamSynchronize(st), "setup sync");
+
+    GmBufs b;
+    b.u = (double2*)(base + L.off_u);
+    b.Q = (double2*)(base + L.off_q);
+    b.qstride = L.qstride_bytes / sizeof(double2);
+    b.pa = (double2*)(base + L.off_pa);
+    b.pb = (double2*)(base + L.off_pb);
+    b.pn = (double*)(base + L.off_pn);
+    b.sig = (double*)(base + L.off_sig);
+    b.R = (double2*)(base + L.off_R);
+    b.cs = (double*)(base + L.off_cs);
+    b.sn = (double2*)(base + L.off_sn);
+    b.gv = (double2*)(base + L.off_g);
+    b.y = (double2*)(base + L.off_y);
+    b.x0n = (double*)(base + L.off_x0n);
+    b.rows = L.rows;
+    b.ldx = L.ldx;
+    b.nch = L.nch;
+
+    const int bs_max = block_sites < n_src ? block_sites : n_src;
+    double worst_err = 0.0, worst_rho = 0.0;
+    int final_code = SCD_OK;
+    for (int blk_start = 0; blk_start < n_src; blk_start += bs_max) {
+        const int bs = (n_src - blk_start) < bs_max ? (n_src - blk_start) : bs_max;
+        const int* src_blk = src_dev + blk_start;
+        SweepArgs a;
+        a.Lx = g.Lx;
+        a.Ly = g.Ly;
+        a.periodic = g.periodic;
+        a.n_r = g.n_r;
+        a.n_t = g.n_t;
+        a.ldx = L.ldx;
+        a.ntn = L.ntn;
+        a.bs = bs;
+        a.lc_sweep = 0;
+        a.group = site_group(g);
+        a.x0_kind = X0_BLOCK;
+        a.x0_fixed = 0;
+        a.sites = nullptr;
+        a.n_sites = g.n_r;
+        a.part_off = 0;
+        a.check = 1;
+        sv.pair_counts(src + blk_start, bs);
+        SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, X0_BLOCK, 0, b.u,
+                                  nullptr, st),
+                "init_block launch");
+        BlockResult res;
+        const int code = sv.solve_gmres(a, src_blk, b, restart, tol, max_iter, &res);
+        if (code == SCD_EHIP) return finish(code);
+        if (code == SCD_ENOTCONV)
+            fail(SCD_ENOTCONV, "block at source %d not converged after %d GMRES steps (e=%g)",
+                 blk_start, max_iter, res.err);
+        stats.n_blocks++;
+        stats.sweeps_total += res.sweeps;
+        if (res.sweeps > stats.sweeps_max) stats.sweeps_max = res.sweeps;
+        worst_err = std::max(worst_err, res.err);
+        worst_rho = std::max(worst_rho, res.rho);
         SCD_HIP(launch_extract(g, res.X, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
                                (double2*)G_loc, (double2*)G_nn, st),
                 "extract launch");

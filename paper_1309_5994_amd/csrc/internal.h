@@ -51,6 +51,8 @@ struct SweepArgs {
     int check;      // 1: read old values and reduce the increment; 0: write only
     void* out2 = nullptr;  // RESIDUAL: second destination of R (the start of the
                            // correction sweeps), or nullptr
+    int no_x0 = 0;         // SOLVE: leave out X0, Y = St^T N(X) (the batched matvec of GMRES)
+    int out_f64 = 0;       // RESIDUAL: write R as complex128 instead of complex64
 };
 
 // X0 of a column block (the preconditioned unit-vector bundle):
@@ -140,6 +142,46 @@ hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipSt
 hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st);
+// ---- batched GMRES (gmres.hip) ----
+// Krylov vectors a cycle may dot against (the restart length limit).
+constexpr int kMaxBasis = 16;
+enum { GS_DOTS = 0, GS_UPDATE_DOTS = 1, GS_UPDATE_NORM = 2, GS_NORM = 3, GS_UPDATE = 4 };
+// One streaming pass over the basis q_i = sig_i v_i (i < k) and a vector w.
+struct GsPass {
+    const double2* Q;     // v_0; v_i at Q + i * qstride
+    size_t qstride;       // elements between basis vectors
+    int k;                // basis vectors used
+    const double* sig;    // [kMaxBasis + 1][ldx] column scales of the basis
+    double2* w;           // vector read (and written by the UPDATE passes)
+    const double* wsig;   // [ldx] column scale applied to w on reading, or nullptr
+    const double2* coef;  // UPDATE: c_i = sum over parts of coef[part][i][column]
+    int coef_parts;
+    size_t coef_pstride;  // elements between parts
+    double2* pdot;        // DOTS: [chunk][kMaxBasis][ldx] partial <q_i, x>
+    double* pnorm;        // NORM: [chunk][ldx] partial |x|^2
+    int rows, ldx, chunk_rows;
+};
+// Per-column Hessenberg / Givens state of one Arnoldi step d (d < 0: cycle start).
+struct GivensArgs {
+    const double2* pa;    // [nch][kMaxBasis][ldx] first Gram-Schmidt dots
+    const double2* pb;    // [nch][kMaxBasis][ldx] second Gram-Schmidt dots
+    const double* pn;     // [nch][ldx] partial squared norms
+    int nch, d, ldx;
+    double* sig;          // [kMaxBasis + 1][ldx]: writes sig[d + 1] (sig[0] at a start)
+    double2* R;           // [kMaxBasis][kMaxBasis][ldx] rotated Hessenberg (row, column)
+    double* cs;           // [kMaxBasis][ldx] rotation cosines
+    double2* sn;          // [kMaxBasis][ldx] rotation sines
+    double2* gv;          // [kMaxBasis + 1][ldx] rotated right-hand side
+    const double* x0n;    // [ldx] |S e| of every column
+    double* part;         // per-workgroup (max residual ratio, 1, bad) triples
+};
+int gs_chunks(int rows, int ldx);
+hipError_t launch_gs(int mode, const GsPass& p, hipStream_t st);
+hipError_t launch_givens(const GivensArgs& a, hipStream_t st);
+hipError_t launch_gmres_solve(const double2* R, const double2* gv, double2* y, int k, int ldx,
+                              hipStream_t st);
+hipError_t launch_colnorm(const double* pn, int nch, int ldx, double* out, hipStream_t st);
+
 hipError_t launch_axpy_f32_to_f64(double2* X, const void* D32, size_t n, hipStream_t st);
 hipError_t launch_adjoint_grads(const Geom& g, int ldx, int e, const double2* H, const double2* Gc,
                                 const double* V, const double* U, const double* J, const double* w,

@@ -43,9 +43,11 @@
 // checks from the measured contraction rate.
 //
 // Modes:
-//  * SOLVE     (FP64): X0 from S; writes Y; partials max|Y - X|, max|Y|.
-//  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64; partials
-//              max|R|, max|Y|.  The FP64 residual of iterative refinement.
+//  * SOLVE     (FP64): X0 from S (or none: the matvec St^T N(X) of GMRES);
+//              writes Y; partials max|Y - X|, max|Y|.
+//  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64 (the FP64
+//              residual of iterative refinement) or complex128 (the residual
+//              GMRES restarts from); partials max|R|, max|Y|.
 //  * CORRECT   (FP32): X0 is a complex64 residual R; X is the correction D;
 //              writes D' = R + St^T (sum of neighbours of D); partials
 //              max|D' - D|, max|D'|.
@@ -323,7 +325,8 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     const int col = n0 + wc * 16 + l16;
     const int s_src = col / cols_per_src;
     const int bcol = col - s_src * cols_per_src;
-    const bool own = (MODE != MODE_CORRECT) && (s_src < g.bs) && (src_blk[s_src] == i);
+    const bool own =
+        (MODE != MODE_CORRECT) && !g.no_x0 && (s_src < g.bs) && (src_blk[s_src] == i);
     const dvec2* Si = S + (size_t)i * g.n_t * g.n_t;
     const cplx* Xi = X + (size_t)i * MP * ldx;
     const size_t site_off = (size_t)i * MP * ldx;
@@ -366,6 +369,8 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                 const double dr = re - (double)old.x, di = im - (double)old.y;
                 if (MODE == MODE_SOLVE) {
                     reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{re, im};
+                } else if (g.out_f64) {
+                    reinterpret_cast<dvec2*>(out)[site_off + off] = dvec2{dr, di};
                 } else {
                     reinterpret_cast<fvec2*>(out)[site_off + off] = fvec2{(float)dr, (float)di};
                     if (g.out2)

@@ -45,7 +45,9 @@ class Stats(ctypes.Structure):
                 ("gemm_flops", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("sweep_kernel_seconds", ctypes.c_double),
                 ("lowp_kernel_seconds", ctypes.c_double),
-                ("sweep_launches", ctypes.c_int32), ("lowp_launches", ctypes.c_int32)]
+                ("sweep_launches", ctypes.c_int32), ("lowp_launches", ctypes.c_int32),
+                ("stream_kernel_seconds", ctypes.c_double), ("stream_bytes", ctypes.c_double),
+                ("stream_launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -84,6 +86,13 @@ def lib():
     L.dyson_iterate.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.scd_gmres_workspace_bytes.restype = ctypes.c_int
+    L.scd_gmres_workspace_bytes.argtypes = [_P(Problem), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32, _P(ctypes.c_size_t)]
+    L.dyson_gmres.restype = ctypes.c_int
+    L.dyson_gmres.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                              _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
     L.local_observables.restype = ctypes.c_int
     L.local_observables.argtypes = [_P(Problem), _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]
     L.scd_adjoint_workspace_bytes.restype = ctypes.c_int
@@ -198,6 +207,54 @@ def dyson_iterate(prob: Problem, S, J, src, block_sites=None, prec=PREC_FP64, to
                              float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc), _ptr(G_nn),
                              _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
                              _stream(stream))
+    _check(rc, st.as_dict())
+    return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
+
+
+def gmres_workspace_bytes(prob: Problem, n_src, block_sites, restart) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_gmres_workspace_bytes(ctypes.byref(prob), int(n_src), int(block_sites),
+                                           int(restart), ctypes.byref(out)))
+    return out.value
+
+
+def _outputs(prob, n_src, dev, out, want_cols, want_nn):
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    out = dict(out or {})
+    G_loc = out.get("G_loc")
+    if G_loc is None:
+        G_loc = torch.empty((n_src, n_t, n_t), dtype=torch.complex128, device=dev)
+    G_nn = out.get("G_nn")
+    if want_nn and G_nn is None:
+        G_nn = torch.empty((n_src, 4, n_t, n_t), dtype=torch.complex128, device=dev)
+    G_cols = out.get("G_cols")
+    if want_cols and G_cols is None:
+        G_cols = torch.empty((n_r, n_t, n_src * n_t), dtype=torch.complex128, device=dev)
+    return G_loc, G_nn, G_cols
+
+
+def dyson_gmres(prob: Problem, S, J, src, block_sites=None, restart=8, tol=1e-12,
+                max_iter=500, want_cols=False, want_nn=True, ws=None, out=None, stream=None):
+    """Columns of G for the source sites ``src`` by preconditioned restarted
+    GMRES (App. C); same outputs as ``dyson_iterate``."""
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+    n_src = int(src.size)
+    block_sites = n_src if block_sites is None else int(block_sites)
+    _need(S, torch.complex128, (n_r, n_t, n_t), "S")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    G_loc, G_nn, G_cols = _outputs(prob, n_src, S.device, out, want_cols, want_nn)
+    need = gmres_workspace_bytes(prob, n_src, block_sites, restart)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=S.device)
+    st = Stats()
+    rc = lib().dyson_gmres(ctypes.byref(prob), _ptr(S), _ptr(J),
+                           src.ctypes.data_as(_P(ctypes.c_int32)), n_src, block_sites,
+                           int(restart), float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc),
+                           _ptr(G_nn), _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
+                           _stream(stream))
     _check(rc, st.as_dict())
     return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
 

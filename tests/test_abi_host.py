@@ -84,3 +84,28 @@ def test_sigma_build_and_observables_reject_nulls():
     assert L.sigma_build(ctypes.byref(p), None, None, None, None) == B.SCD_EINVAL
     assert L.local_observables(ctypes.byref(p), None, None, None, 1, None, None, None) == B.SCD_EINVAL
     assert L.sigma_build(None, None, None, None, None) == B.SCD_EINVAL
+
+
+def test_gmres_workspace_and_validation():
+    p = B.problem(4, 4, 20, 10, 0.1, 5.0)
+    # St + iterate + restart + 1 basis vectors (16 x 64 x 800 complex128 each)
+    it = 16 * 64 * 800 * 16
+    n = B.gmres_workspace_bytes(p, 16, 16, 4)
+    assert n >= 16 * 64 * 64 * 16 + 6 * it
+    assert B.gmres_workspace_bytes(p, 16, 16, 8) - n >= 4 * it
+    out = ctypes.c_size_t(0)
+    for bad in (0, 17):
+        assert B.lib().scd_gmres_workspace_bytes(ctypes.byref(p), 16, 16, bad,
+                                                 ctypes.byref(out)) == B.SCD_EINVAL
+        assert "restart" in B.last_error()
+    L = B.lib()
+    src = np.array([0, 3], dtype=np.int32)
+    fake = ctypes.c_void_p(0x1000)                   # never dereferenced
+    st = B.Stats()
+    args = lambda restart, tol, ws_bytes: (
+        ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 2, 2,
+        restart, tol, 10, None, fake, None, fake, ctypes.c_size_t(ws_bytes), ctypes.byref(st), None)
+    assert L.dyson_gmres(*args(0, 1e-12, 1 << 40)) == B.SCD_EINVAL and "restart" in B.last_error()
+    assert L.dyson_gmres(*args(4, -1.0, 1 << 40)) == B.SCD_EINVAL and "tol" in B.last_error()
+    assert L.dyson_gmres(*args(4, 1e-12, 64)) == B.SCD_ENOMEM
+    assert st.status == B.SCD_ENOMEM

@@ -60,7 +60,10 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
-                    help="skip the FP64-vs-mixed time-to-solution legs (profiling runs)")
+                    help="skip the time-to-solution and adjoint legs (profiling runs)")
+    ap.add_argument("--legs", default="fp64,mixed,gmres,adjoint",
+                    help="comma list of extra legs: fp64, mixed, gmres, adjoint")
+    ap.add_argument("--gmres-restart", type=int, default=6)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -86,6 +89,41 @@ def cpu_baseline(wl, flops_per_source):
                       f"LU (scipy/OpenBLAS), {secs:.1f} s incl. S build; value = GPU-path "
                       f"algorithmic flops for that source / oracle time",
             "seconds": secs}
+
+
+def gmres_leg(B, prob, S, V, U, J, src, block, n_ref, restart):
+    """Time to a converged G by the batched preconditioned GMRES(restart) of
+    App. C (dyson_gmres, FP64), with its split into batched matvecs (sweep
+    kernel) and streaming passes (Gram-Schmidt, Givens, update); the streaming
+    rate is algorithmic bytes (each Krylov vector read or written once per
+    pass) over their HIP-event time, against the 8 TB/s HBM peak."""
+    import torch
+    out = {}
+    ws = torch.empty(B.gmres_workspace_bytes(prob, len(src), block, restart), dtype=torch.uint8,
+                     device=S.device)
+    for tol in (1e-9, 1e-12):
+        for rep in range(2):          # first repetition warms up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            B.sigma_build(prob, V, U, S)
+            r = B.dyson_gmres(prob, S, J, src, block_sites=block, restart=restart, tol=tol,
+                              max_iter=500, ws=ws)
+            n_g, _ = B.local_observables(prob, r["G_loc"], r["G_nn"], J)
+            torch.cuda.synchronize()
+            t_g = time.perf_counter() - t1
+        st = r["stats"]
+        gbs = st["stream_bytes"] / max(st["stream_kernel_seconds"], 1e-12) / 1e9
+        out[f"gmres{restart}_fp64_tol{tol:g}"] = {
+            "seconds": round(t_g, 4), "max_abs_dn": float((n_g - n_ref).abs().max()),
+            "arnoldi_steps": st["sweeps_total"], "matvecs": st["fp64_sweeps"],
+            "final_rel_residual": st["final_err"], "residual_ratio_per_step": st["rho_est"],
+            "matvec_kernel_ms": round(1e3 * st["sweep_kernel_seconds"], 2),
+            "stream_kernel_ms": round(1e3 * st["stream_kernel_seconds"], 2),
+            "stream_GBps": round(gbs, 1), "stream_frac_of_hbm_peak": round(gbs / 8000.0, 4),
+            "workspace_GB": round(ws.numel() / 1e9, 1)}
+    del ws
+    torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_leg(B, prob, S, V, U, J, wl, forward_full_s):
@@ -195,12 +233,15 @@ def main():
     # errors are measured against the FP64 run at 1e-12 above.
     n_ref = n.clone()
     tts = {}
-    legs = () if args.quick else (("fp64_tol1e-12", B.PREC_FP64, args.tol),
-                                  ("fp64_tol1e-9", B.PREC_FP64, 1e-9),
-                                  ("mixed_fp32_tol1e-9", B.PREC_FP32, 1e-9),
-                                  ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12),
-                                  ("mixed_bf16x3_tol1e-9", B.PREC_BF16X3, 1e-9),
-                                  ("mixed_bf16x3_tol1e-12", B.PREC_BF16X3, 1e-12))
+    want = set() if args.quick else set(args.legs.split(","))
+    legs = ()
+    if "fp64" in want:
+        legs += (("fp64_tol1e-12", B.PREC_FP64, args.tol), ("fp64_tol1e-9", B.PREC_FP64, 1e-9))
+    if "mixed" in want:
+        legs += (("mixed_fp32_tol1e-9", B.PREC_FP32, 1e-9),
+                 ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12),
+                 ("mixed_bf16x3_tol1e-9", B.PREC_BF16X3, 1e-9),
+                 ("mixed_bf16x3_tol1e-12", B.PREC_BF16X3, 1e-12))
     for label, prec, tol in legs:
         ws_p = ws if prec == B.PREC_FP64 else torch.empty(
             B.workspace_bytes(prob, len(src), block, prec), dtype=torch.uint8, device=dev)
@@ -221,9 +262,11 @@ def main():
                       "fp64_kernel_ms": round(1e3 * st_p["sweep_kernel_seconds"], 2),
                       "lowp_kernel_ms": round(1e3 * st_p["lowp_kernel_seconds"], 2),
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
+    if "gmres" in want:
+        tts.update(gmres_leg(B, prob, S, V, U, J, src, block, n_ref, args.gmres_restart))
     if tts:
         rec["time_to_solution"] = tts
-    if not args.quick:
+    if "adjoint" in want:
         rec["adjoint"] = adjoint_leg(B, prob, S, V, U, J, wl, rec["time_to_solution_s"])
     if not args.no_cpu:
         per_source = stats[-1]["gemm_flops"] / len(src)

@@ -179,8 +179,9 @@ int scd_gmres_workspace_bytes(const scd_problem* p, int32_t n_src, int32_t block
  *   restart    Krylov vectors per cycle, 1..16; the workspace holds restart + 2
  *              iterates of a block (size block_sites to fit HBM)
  *   tol        stop when every column's preconditioned residual 2-norm is at most
- *              tol times the 2-norm of its S e (checked after every Arnoldi step
- *              through the rotated Hessenberg system)
+ *              tol times the 2-norm of its S e: a cycle ends early when the
+ *              rotated Hessenberg system says so (checked after every Arnoldi
+ *              step), and the residual recomputed in FP64 from the iterate decides
  *   max_iter   Arnoldi steps (batched matvecs) per block
  *   other arguments as dyson_iterate; FP64 throughout.
  * st: sweeps_total / sweeps_max count Arnoldi steps; fp64_sweeps every batched

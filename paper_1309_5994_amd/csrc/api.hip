@@ -484,8 +484,10 @@ struct Solver {
     // (the preconditioned residual S e - (I - S D) u) becomes v_0; each Arnoldi
     // step is one batched matvec w = St^T N(v_d) (sweep kernel without X0)
     // followed by classical Gram-Schmidt applied twice and the Givens update of
-    // every column's Hessenberg system.  Stops when the largest relative
-    // residual |g_{d+1}| / |X0| over the columns is at most tol.
+    // every column's Hessenberg system.  A cycle ends after `restart` steps or
+    // once the largest rotated residual |g_{d+1}| / |X0| over the columns is at
+    // most tol; the block has converged when the recomputed FP64 residual
+    // |z| / |X0| of every column is at most tol.
     int solve_gmres(SweepArgs a, const int* src_blk, const GmBufs& b, int restart, double tol,
                     int max_iter, BlockResult* res) {
         const int cps = g.n_t;
@@ -593,15 +595,14 @@ struct Solver {
                 q.w = w;
                 q.wsig = b.sig + (size_t)d * b.ldx;     // T q_d = sig_d T v_d
                 q.pdot = b.pa;
-                if (gs(GS_DOTS, q, k + 1)) return SCD_EHIP;
+                if (gs(GS_DOTS, q, k + 1)) return SCD_EHIP;          // h1
                 q.coef = b.pa;
                 q.coef_parts = b.nch;
                 q.coef_pstride = pstride;
                 q.pdot = b.pb;
-                if (gs(GS_UPDATE_DOTS, q, k + 2)) return SCD_EHIP;
-                q.wsig = nullptr;
-                q.coef = b.pb;
-                if (gs(GS_UPDATE_NORM, q, k + 2)) return SCD_EHIP;
+                if (gs(GS_PROJ_DOTS, q, k + 1)) return SCD_EHIP;     // h2
+                q.coef2 = b.pb;
+                if (gs(GS_UPDATE_NORM, q, k + 2)) return SCD_EHIP;   // v_{d+1}, |v_{d+1}|
                 ga.d = d;
                 SCD_HIP(ts.mark(st), "event record");
                 SCD_HIP(launch_givens(ga, st), "Givens launch");
@@ -613,8 +614,7 @@ struct Solver {
                     break;
                 }
                 e = r[0];
-                if (e <= tol) code = SCD_OK;
-                if (code == SCD_OK || n >= max_iter || d == restart - 1) {
+                if (e <= tol || n >= max_iter || d == restart - 1) {
                     // u += sum_i y_i q_i over the k basis vectors of this cycle.
                     SCD_HIP(ts.mark(st), "event record");
                     SCD_HIP(launch_gmres_solve(b.R, b.gv, b.y, k, b.ldx, st), "solve launch");
@@ -630,7 +630,9 @@ struct Solver {
                     break;
                 }
             }
-            if (code != SCD_ENOTCONV || n >= max_iter) break;
+            // Back to the top: convergence (and the reported error) is decided on
+            // the residual recomputed in FP64 from u, not on the rotated estimate.
+            if (code == SCD_ENAN) break;
         }
         double tail[3];
         if (reduce(tail, ngw)) return SCD_EHIP;     // drains the last timings

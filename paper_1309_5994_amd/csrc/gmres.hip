@@ -14,12 +14,17 @@
 //
 // Streaming passes (HBM-bound): one 16-byte complex per thread and row, each
 // wave 64 consecutive columns (1 KB per row), four waves on interleaved rows:
-//   DOTS          p_i = sum_rows conj(q_i) x,         x = ws w
-//   UPDATE_DOTS   x = ws w - sum_i c_i q_i; write x;  p_i = sum_rows conj(q_i) x
-//   UPDATE_NORM   x = w - sum_i c_i q_i; write x;     |x|^2
+//   DOTS          p_i = sum_rows conj(q_i) x,            x = ws w
+//   PROJ_DOTS     x = ws w - sum_i c_i q_i (registers);  p_i = sum_rows conj(q_i) x
+//   UPDATE_NORM   x = ws w - sum_i c_i q_i; write x;     |x|^2
 //   NORM          |w|^2
 //   UPDATE        w = w - sum_i c_i q_i (the solution update, c = -y)
-// with i < k.  A workgroup covers 64 columns and one chunk of rows; partial
+// with i < k.  Classical Gram-Schmidt applied twice is DOTS (h1), PROJ_DOTS
+// with c = h1 (h2, the dots of the once-projected vector, which is not
+// stored) and UPDATE_NORM with c = h1 + h2 from the matvec output again: the
+// same projections as two stored passes, with one vector less moved per step
+// and a read-only middle pass.  Krylov vectors are read with non-temporal
+// loads (streamed once per pass, no reuse in the caches).  A workgroup covers 64 columns and one chunk of rows; partial
 // sums go to [chunk][i][column] and their consumer adds the chunks in order,
 // so results do not depend on scheduling (no atomics).
 #include "internal.h"
@@ -38,7 +43,7 @@ __device__ inline dvec2 cmulc(dvec2 a, dvec2 b) {
     return dvec2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
 }
 
-template <int KB, bool UPDATE, bool DOTS, bool NORM>
+template <int KB, bool UPDATE, bool DOTS, bool NORM, bool WRITE>
 __global__ __launch_bounds__(kGsThreads)
 void gs_kernel(GsPass p) {
     __shared__ dvec2 red[kGsThreads];
@@ -49,6 +54,7 @@ void gs_kernel(GsPass p) {
     const dvec2* Q = reinterpret_cast<const dvec2*>(p.Q);
     dvec2* w = reinterpret_cast<dvec2*>(p.w);
     const dvec2* coef = reinterpret_cast<const dvec2*>(p.coef);
+    const dvec2* coef2 = reinterpret_cast<const dvec2*>(p.coef2);
 
     // The column scales enter outside the row loop: the update uses
     // c_i sig_i, the dots are sig_i sum conj(v_i) x.
@@ -59,6 +65,9 @@ void gs_kernel(GsPass p) {
         if (UPDATE && i < p.k) {
             for (int q = 0; q < p.coef_parts; ++q)
                 cf[i] += coef[(size_t)q * p.coef_pstride + (size_t)i * p.ldx + cc];
+            if (coef2)
+                for (int q = 0; q < p.coef_parts; ++q)
+                    cf[i] += coef2[(size_t)q * p.coef_pstride + (size_t)i * p.ldx + cc];
             cf[i] *= p.sig[(size_t)i * p.ldx + cc];
         }
     }
@@ -72,11 +81,12 @@ void gs_kernel(GsPass p) {
     const int r1 = min(p.rows, r0 + p.chunk_rows);
     for (int r = r0 + wv; r < r1; r += 4) {
         const size_t off = (size_t)r * p.ldx + cc;
-        dvec2 x = w[off] * ws;
+        dvec2 x = __builtin_nontemporal_load(&w[off]) * ws;
         dvec2 v[KB];
 #pragma unroll
         for (int i = 0; i < KB; ++i)
-            v[i] = i < p.k ? Q[(size_t)i * p.qstride + off] : dvec2{0.0, 0.0};
+            v[i] = i < p.k ? __builtin_nontemporal_load(&Q[(size_t)i * p.qstride + off])
+                           : dvec2{0.0, 0.0};
         if (UPDATE) {
 #pragma unroll
             for (int i = 0; i < KB; ++i) x -= cmul(cf[i], v[i]);
@@ -86,7 +96,7 @@ void gs_kernel(GsPass p) {
             for (int i = 0; i < KB; ++i) acc[i] += cmulc(v[i], x);
         }
         if (NORM) nrm += x.x * x.x + x.y * x.y;
-        if (UPDATE && live) w[off] = x;
+        if (WRITE && live) w[off] = x;
     }
     if (DOTS) {
 #pragma unroll
@@ -261,16 +271,20 @@ template <int KB>
 hipError_t launch_gs_kb(int mode, const GsPass& p, dim3 grid, hipStream_t st) {
     switch (mode) {
         case GS_DOTS:
-            hipLaunchKernelGGL((gs_kernel<KB, false, true, false>), grid, dim3(kGsThreads), 0, st, p);
+            hipLaunchKernelGGL((gs_kernel<KB, false, true, false, false>), grid, dim3(kGsThreads), 0,
+                               st, p);
             break;
-        case GS_UPDATE_DOTS:
-            hipLaunchKernelGGL((gs_kernel<KB, true, true, false>), grid, dim3(kGsThreads), 0, st, p);
+        case GS_PROJ_DOTS:
+            hipLaunchKernelGGL((gs_kernel<KB, true, true, false, false>), grid, dim3(kGsThreads), 0,
+                               st, p);
             break;
         case GS_UPDATE_NORM:
-            hipLaunchKernelGGL((gs_kernel<KB, true, false, true>), grid, dim3(kGsThreads), 0, st, p);
+            hipLaunchKernelGGL((gs_kernel<KB, true, false, true, true>), grid, dim3(kGsThreads), 0,
+                               st, p);
             break;
         case GS_UPDATE:
-            hipLaunchKernelGGL((gs_kernel<KB, true, false, false>), grid, dim3(kGsThreads), 0, st, p);
+            hipLaunchKernelGGL((gs_kernel<KB, true, false, false, true>), grid, dim3(kGsThreads), 0,
+                               st, p);
             break;
         default: return hipErrorInvalidValue;
     }
@@ -293,7 +307,8 @@ hipError_t launch_gs(int mode, const GsPass& p, hipStream_t st) {
         return hipErrorInvalidValue;
     const dim3 grid((p.ldx + kGsCols - 1) / kGsCols, (p.rows + p.chunk_rows - 1) / p.chunk_rows);
     if (mode == GS_NORM) {
-        hipLaunchKernelGGL((gs_kernel<1, false, false, true>), grid, dim3(kGsThreads), 0, st, p);
+        hipLaunchKernelGGL((gs_kernel<1, false, false, true, false>), grid, dim3(kGsThreads), 0, st,
+                           p);
         return hipGetLastError();
     }
     if (p.k < 1) return hipErrorInvalidValue;

@@ -145,7 +145,7 @@ hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf
 // ---- batched GMRES (gmres.hip) ----
 // Krylov vectors a cycle may dot against (the restart length limit).
 constexpr int kMaxBasis = 16;
-enum { GS_DOTS = 0, GS_UPDATE_DOTS = 1, GS_UPDATE_NORM = 2, GS_NORM = 3, GS_UPDATE = 4 };
+enum { GS_DOTS = 0, GS_PROJ_DOTS = 1, GS_UPDATE_NORM = 2, GS_NORM = 3, GS_UPDATE = 4 };
 // One streaming pass over the basis q_i = sig_i v_i (i < k) and a vector w.
 struct GsPass {
     const double2* Q;     // v_0; v_i at Q + i * qstride
@@ -155,6 +155,7 @@ struct GsPass {
     double2* w;           // vector read (and written by the UPDATE passes)
     const double* wsig;   // [ldx] column scale applied to w on reading, or nullptr
     const double2* coef;  // UPDATE: c_i = sum over parts of coef[part][i][column]
+    const double2* coef2; //   (+ the same sum over coef2 if not nullptr)
     int coef_parts;
     size_t coef_pstride;  // elements between parts
     double2* pdot;        // DOTS: [chunk][kMaxBasis][ldx] partial <q_i, x>

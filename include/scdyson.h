@@ -156,6 +156,34 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J,
                   void* ws, size_t ws_bytes, scd_stats* st, void* stream);
 
 /*
+ * Device workspace (bytes) that dyson_iterate_sym needs for the sources src
+ * (host int32[n_src]) in column blocks of block_sites representatives.
+ */
+int scd_sym_workspace_bytes(const scd_problem* p, const int32_t* src, int32_t n_src,
+                            int32_t block_sites, int32_t prec, size_t* bytes);
+
+/*
+ * dyson_iterate reduced by the lattice's point group (App. A).  When every
+ * site's atomic Green's function is invariant under the point group about the
+ * lattice centre (C4v for Lx == Ly: the two mirrors and the diagonal; C2v for
+ * Lx != Ly), so is G: G(g(i), g(j)) = G(i, j) for every element g (the
+ * hopping is uniform).  Only one source per orbit is solved (the smallest
+ * site index of each orbit the requested sources meet: 36 of 256 on a 16x16
+ * lattice), and the outputs of every requested source s = g(r) are copied from
+ * its representative r, target sites mapped by g^-1 and neighbour slots
+ * relabelled; they are bitwise those of r.
+ * Arguments, outputs and errors as dyson_iterate (block_sites counts
+ * representatives; the workspace is scd_sym_workspace_bytes()), plus
+ * SCD_EINVAL if max |S_i - S_g(i)| over the group's generators exceeds 1e-12
+ * (checked on the device before any sweep).
+ */
+int dyson_iterate_sym(const scd_problem* p, const void* S, const double* J,
+                      const int32_t* src, int32_t n_src, int32_t block_sites,
+                      int32_t prec, double tol, int32_t max_iter,
+                      void* G_cols, void* G_loc, void* G_nn,
+                      void* ws, size_t ws_bytes, scd_stats* st, void* stream);
+
+/*
  * Device workspace (bytes) that dyson_gmres needs for n_src source sites in
  * column blocks of block_sites sources with `restart` Krylov vectors per cycle.
  * Returns SCD_OK and writes *bytes, or SCD_EINVAL.

@@ -693,10 +693,75 @@ int local_observables(const scd_problem* p, const void* G_loc, const void* G_nn,
     return SCD_OK;
 }
 
-int dyson_iterate(const scd_problem* p, const void* S, const double* J, const int32_t* src,
-                  int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
-                  void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
-                  scd_stats* st_out, void* stream) {
+namespace {
+
+// Requested sources of a point-group-reduced solve: the representatives to
+// solve, and per requested source (sorted by its representative's position)
+// the position within its column block, the group element and the slot map.
+struct SymPlan {
+    SymGroup grp;
+    std::vector<int32_t> reps, req, req_lr, req_g, req_slot, req_pos;
+    size_t off_perm = 0, off_perm_inv = 0, off_req = 0, off_lr = 0, off_g = 0, off_slot = 0,
+           off_check = 0, total = 0;
+};
+
+constexpr int kSymCheckParts = 256;
+
+int sym_plan(const Geom& g, const int32_t* src, int n_src, int block_sites, size_t base,
+             SymPlan* P) {
+    P->grp = lattice_group(g);
+    std::vector<int> pos(g.n_r, -1);
+    for (int s = 0; s < n_src; ++s) {
+        const int r = P->grp.rep[src[s]];
+        if (pos[r] < 0) {
+            pos[r] = (int)P->reps.size();
+            P->reps.push_back(r);
+        }
+    }
+    const int bs_max = std::min(block_sites, (int)P->reps.size());
+    std::vector<int> order(n_src);
+    for (int s = 0; s < n_src; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return pos[P->grp.rep[src[a]]] < pos[P->grp.rep[src[b]]];
+    });
+    for (int s : order) {
+        const int rp = pos[P->grp.rep[src[s]]];
+        P->req.push_back(s);
+        P->req_pos.push_back(rp);
+        P->req_lr.push_back(rp % bs_max);
+        P->req_g.push_back(P->grp.elem[src[s]]);
+        for (int d = 0; d < 4; ++d) {
+            const int q = sym_slot(P->grp, g, src[s], d);
+            if (q == -2)
+                return fail(SCD_EINVAL, "the lattice point group does not map neighbours of "
+                                        "site %d to neighbours", src[s]);
+            P->req_slot.push_back(q);
+        }
+    }
+    size_t off = base;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t tab = (size_t)P->grp.n_el * g.n_r * sizeof(int32_t);
+    P->off_perm = take(tab);
+    P->off_perm_inv = take(tab);
+    P->off_req = take((size_t)n_src * sizeof(int32_t));
+    P->off_lr = take((size_t)n_src * sizeof(int32_t));
+    P->off_g = take((size_t)n_src * sizeof(int32_t));
+    P->off_slot = take((size_t)n_src * 4 * sizeof(int32_t));
+    P->off_check = take(kSymCheckParts * sizeof(double));
+    P->total = off;
+    return SCD_OK;
+}
+
+// dyson_iterate and dyson_iterate_sym: the sweeps over the column blocks of
+// `src` (sym: of the orbit representatives of `src`).
+int iterate_impl(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                 int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
+                 void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
+                 scd_stats* st_out, void* stream, bool sym) {
     const auto t_start = std::chrono::steady_clock::now();
     scd_stats stats;
     std::memset(&stats, 0, sizeof stats);
@@ -722,12 +787,67 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     for (int s = 0; s < n_src; ++s)
         if (src[s] < 0 || src[s] >= g.n_r)
             return finish(fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r));
-    const Layout L = layout(g, n_src, block_sites, prec);
-    if (ws_bytes < L.total)
-        return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total));
+    SymPlan plan;
+    const int32_t* solve_src = src;
+    int n_solve = n_src;
+    if (sym) {
+        // Layout of the representatives first, then the symmetry tables after it.
+        SymPlan probe;
+        rc = sym_plan(g, src, n_src, block_sites, 0, &probe);
+        if (rc) return finish(rc);
+        const Layout L0 = layout(g, (int)probe.reps.size(), block_sites, prec);
+        rc = sym_plan(g, src, n_src, block_sites, L0.total, &plan);
+        if (rc) return finish(rc);
+        solve_src = plan.reps.data();
+        n_solve = (int)plan.reps.size();
+    }
+    const Layout L = layout(g, n_solve, block_sites, prec);
+    const size_t need = sym ? plan.total : L.total;
+    if (ws_bytes < need)
+        return finish(fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need));
 
     hipStream_t st = (hipStream_t)stream;
     char* base = (char*)ws;
+    if (sym) {
+        // S must be invariant under the group (checked on the generators).
+        int* perm_dev = (int*)(base + plan.off_perm);
+        const size_t tab = (size_t)plan.grp.n_el * g.n_r * sizeof(int32_t);
+        SCD_HIP(hipMemcpyAsync(perm_dev, plan.grp.perm.data(), tab, hipMemcpyHostToDevice, st),
+                "copy group");
+        SCD_HIP(hipMemcpyAsync(base + plan.off_perm_inv, plan.grp.perm_inv.data(), tab,
+                               hipMemcpyHostToDevice, st),
+                "copy group");
+        const size_t nq = plan.req.size() * sizeof(int32_t);
+        SCD_HIP(hipMemcpyAsync(base + plan.off_req, plan.req.data(), nq, hipMemcpyHostToDevice, st),
+                "copy plan");
+        SCD_HIP(hipMemcpyAsync(base + plan.off_lr, plan.req_lr.data(), nq, hipMemcpyHostToDevice,
+                               st),
+                "copy plan");
+        SCD_HIP(hipMemcpyAsync(base + plan.off_g, plan.req_g.data(), nq, hipMemcpyHostToDevice, st),
+                "copy plan");
+        SCD_HIP(hipMemcpyAsync(base + plan.off_slot, plan.req_slot.data(), 4 * nq,
+                               hipMemcpyHostToDevice, st),
+                "copy plan");
+        double worst = 0.0;
+        const int gens[3] = {1, 2, 4};
+        for (int e : gens) {
+            if (e >= plan.grp.n_el) continue;
+            double part[kSymCheckParts];
+            double* part_dev = (double*)(base + plan.off_check);
+            SCD_HIP(launch_sym_check((const double2*)S, perm_dev + (size_t)e * g.n_r, g, part_dev,
+                                     kSymCheckParts, st),
+                    "symmetry check launch");
+            SCD_HIP(hipMemcpyAsync(part, part_dev, sizeof part, hipMemcpyDeviceToHost, st),
+                    "copy check");
+            SCD_HIP(hipStreamSynchronize(st), "check sync");
+            for (double v : part) worst = (v > worst || v != v) ? v : worst;
+        }
+        if (!(worst <= 1e-12))
+            return finish(fail(SCD_EINVAL,
+                                "S is not invariant under the lattice point group "
+                                "(max |S_i - S_g(i)| = %g)",
+                                worst));
+    }
     Solver sv;
     sv.g = g;
     sv.st = st;
@@ -741,7 +861,8 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     sv.nwg = L.nwg;
     int* src_dev = (int*)(base + L.off_src);
 
-    SCD_HIP(hipMemcpyAsync(src_dev, src, (size_t)n_src * sizeof(int32_t), hipMemcpyHostToDevice, st),
+    SCD_HIP(hipMemcpyAsync(src_dev, solve_src, (size_t)n_solve * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st),
             "copy src");
     const bool bipartite = lattice_bipartite(g);
     int n_even = 0;
@@ -764,11 +885,11 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         SCD_HIP(launch_to_f32(sv.St, sv.St32, (size_t)g.n_r * g.mp * g.mp, st), "St32 launch");
     SCD_HIP(hipStreamSynchronize(st), "setup sync");
 
-    const int bs_max = block_sites < n_src ? block_sites : n_src;
+    const int bs_max = block_sites < n_solve ? block_sites : n_solve;
     double worst_err = 0.0, worst_rho = 0.0;
     int final_code = SCD_OK;
-    for (int blk_start = 0; blk_start < n_src; blk_start += bs_max) {
-        const int bs = (n_src - blk_start) < bs_max ? (n_src - blk_start) : bs_max;
+    for (int blk_start = 0; blk_start < n_solve; blk_start += bs_max) {
+        const int bs = (n_solve - blk_start) < bs_max ? (n_solve - blk_start) : bs_max;
         const int* src_blk = src_dev + blk_start;
         SweepArgs a;
         a.Lx = g.Lx;
@@ -787,7 +908,7 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         a.n_sites = g.n_r;
         a.part_off = 0;
         a.check = 1;
-        sv.pair_counts(src + blk_start, bs);
+        sv.pair_counts(solve_src + blk_start, bs);
         double2* X = (double2*)(base + L.off_x0);
         double2* Xn = L.off_x1 ? (double2*)(base + L.off_x1) : nullptr;
         SCD_HIP(launch_init_block(g, (const double2*)S, src_blk, bs, L.ldx, X0_BLOCK, 0, X, Xn, st),
@@ -809,9 +930,24 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
         if (res.sweeps > stats.sweeps_max) stats.sweeps_max = res.sweeps;
         worst_err = res.err > worst_err ? res.err : worst_err;
         worst_rho = res.rho > worst_rho ? res.rho : worst_rho;
-        SCD_HIP(launch_extract(g, res.X, L.ldx, src_blk, bs, blk_start, n_src, (double2*)G_cols,
-                               (double2*)G_loc, (double2*)G_nn, st),
-                "extract launch");
+        if (sym) {
+            // Every requested source whose representative is in this block.
+            int q0 = 0;
+            while (q0 < n_src && plan.req_pos[q0] < blk_start) ++q0;
+            int q1 = q0;
+            while (q1 < n_src && plan.req_pos[q1] < blk_start + bs) ++q1;
+            SCD_HIP(launch_extract_sym(g, res.X, L.ldx, src_blk, (int*)(base + plan.off_req) + q0,
+                                       (int*)(base + plan.off_lr) + q0,
+                                       (int*)(base + plan.off_g) + q0,
+                                       (int*)(base + plan.off_slot) + 4 * q0,
+                                       (int*)(base + plan.off_perm_inv), q1 - q0, n_src,
+                                       (double2*)G_cols, (double2*)G_loc, (double2*)G_nn, st),
+                    "extract launch");
+        } else {
+            SCD_HIP(launch_extract(g, res.X, L.ldx, src_blk, bs, blk_start, n_src,
+                                   (double2*)G_cols, (double2*)G_loc, (double2*)G_nn, st),
+                    "extract launch");
+        }
         if (code != SCD_OK) {
             final_code = code;
             break;
@@ -822,6 +958,49 @@ int dyson_iterate(const scd_problem* p, const void* S, const double* J, const in
     stats.rho_est = worst_rho;
     if (final_code == SCD_OK) g_last_error.clear();
     return finish(final_code);
+}
+
+}  // namespace
+
+int dyson_iterate(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                  int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
+                  void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
+                  scd_stats* st_out, void* stream) {
+    return iterate_impl(p, S, J, src, n_src, block_sites, prec, tol, max_iter, G_cols, G_loc, G_nn,
+                        ws, ws_bytes, st_out, stream, false);
+}
+
+int dyson_iterate_sym(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                      int32_t n_src, int32_t block_sites, int32_t prec, double tol,
+                      int32_t max_iter, void* G_cols, void* G_loc, void* G_nn, void* ws,
+                      size_t ws_bytes, scd_stats* st_out, void* stream) {
+    return iterate_impl(p, S, J, src, n_src, block_sites, prec, tol, max_iter, G_cols, G_loc, G_nn,
+                        ws, ws_bytes, st_out, stream, true);
+}
+
+int scd_sym_workspace_bytes(const scd_problem* p, const int32_t* src, int32_t n_src,
+                            int32_t block_sites, int32_t prec, size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes || !src) return fail(SCD_EINVAL, "src and bytes must be non-NULL");
+    if (n_src < 1 || n_src > g.n_r) return fail(SCD_EINVAL, "n_src must be in [1, N_r]");
+    if (block_sites < 1) return fail(SCD_EINVAL, "block_sites must be >= 1");
+    if (prec != SCD_PREC_FP64 && prec != SCD_PREC_FP32 && prec != SCD_PREC_BF16X3)
+        return fail(SCD_EINVAL, "unsupported precision %d", prec);
+    for (int s = 0; s < n_src; ++s)
+        if (src[s] < 0 || src[s] >= g.n_r)
+            return fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r);
+    SymPlan probe;
+    rc = sym_plan(g, src, n_src, block_sites, 0, &probe);
+    if (rc) return rc;
+    SymPlan plan;
+    rc = sym_plan(g, src, n_src, block_sites,
+                  layout(g, (int)probe.reps.size(), block_sites, prec).total, &plan);
+    if (rc) return rc;
+    *bytes = plan.total;
+    g_last_error.clear();
+    return SCD_OK;
 }
 
 // ---- GMRES -----------------------------------------------------------------

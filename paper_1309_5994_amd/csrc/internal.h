@@ -142,6 +142,27 @@ hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipSt
 hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st);
+// ---- point-group reduction (sym.hip) ----
+// The lattice's point group about its centre: C4v (8 elements) for Lx == Ly,
+// else C2v (4).  Element e applies mirror x (bit 0), mirror y (bit 1), then
+// the diagonal swap (bit 2).
+struct SymGroup {
+    int n_el = 0;
+    std::vector<int> perm, perm_inv;   // [n_el][n_r]: site images under e and e^-1
+    std::vector<int> rep, elem;        // per site: orbit representative (smallest
+                                       // index) and an element taking it to the site
+};
+SymGroup lattice_group(const Geom& g);
+// Neighbour slot of rep(s) that slot d of s maps to under elem(s)^-1 (-1: no
+// neighbour; -2: the element does not preserve the neighbour structure).
+int sym_slot(const SymGroup& G, const Geom& g, int s, int d);
+hipError_t launch_sym_check(const double2* S, const int* perm, const Geom& g, double* part,
+                            int n_part, hipStream_t st);
+hipError_t launch_extract_sym(const Geom& g, const double2* X, int ldx, const int* src_blk,
+                              const int* req, const int* req_lr, const int* req_g,
+                              const int* req_slot, const int* perm_inv, int n_req, int n_src,
+                              double2* G_cols, double2* G_loc, double2* G_nn, hipStream_t st);
+
 // ---- batched GMRES (gmres.hip) ----
 // Krylov vectors a cycle may dot against (the restart length limit).
 constexpr int kMaxBasis = 16;

@@ -86,6 +86,11 @@ def lib():
     L.dyson_iterate.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.scd_sym_workspace_bytes.restype = ctypes.c_int
+    L.scd_sym_workspace_bytes.argtypes = [_P(Problem), _P(ctypes.c_int32), ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_size_t)]
+    L.dyson_iterate_sym.restype = ctypes.c_int
+    L.dyson_iterate_sym.argtypes = L.dyson_iterate.argtypes
     L.scd_gmres_workspace_bytes.restype = ctypes.c_int
     L.scd_gmres_workspace_bytes.argtypes = [_P(Problem), ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_int32, _P(ctypes.c_size_t)]
@@ -207,6 +212,41 @@ def dyson_iterate(prob: Problem, S, J, src, block_sites=None, prec=PREC_FP64, to
                              float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc), _ptr(G_nn),
                              _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
                              _stream(stream))
+    _check(rc, st.as_dict())
+    return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
+
+
+def sym_workspace_bytes(prob: Problem, src, block_sites, prec=PREC_FP64) -> int:
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_sym_workspace_bytes(ctypes.byref(prob), src.ctypes.data_as(_P(ctypes.c_int32)),
+                                         int(src.size), int(block_sites), int(prec),
+                                         ctypes.byref(out)))
+    return out.value
+
+
+def dyson_iterate_sym(prob: Problem, S, J, src, block_sites=None, prec=PREC_FP64, tol=1e-12,
+                      max_iter=500, want_cols=False, want_nn=True, ws=None, out=None,
+                      stream=None):
+    """``dyson_iterate`` with only one source per point-group orbit solved (App. A);
+    same outputs for every requested source."""
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+    n_src = int(src.size)
+    block_sites = n_src if block_sites is None else int(block_sites)
+    _need(S, torch.complex128, (n_r, n_t, n_t), "S")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    G_loc, G_nn, G_cols = _outputs(prob, n_src, S.device, out, want_cols, want_nn)
+    need = sym_workspace_bytes(prob, src, block_sites, prec)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=S.device)
+    st = Stats()
+    rc = lib().dyson_iterate_sym(ctypes.byref(prob), _ptr(S), _ptr(J),
+                                 src.ctypes.data_as(_P(ctypes.c_int32)), n_src, block_sites,
+                                 int(prec), float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc),
+                                 _ptr(G_nn), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                 ctypes.byref(st), _stream(stream))
     _check(rc, st.as_dict())
     return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
 

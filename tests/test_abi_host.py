@@ -109,3 +109,18 @@ def test_gmres_workspace_and_validation():
     assert L.dyson_gmres(*args(4, -1.0, 1 << 40)) == B.SCD_EINVAL and "tol" in B.last_error()
     assert L.dyson_gmres(*args(4, 1e-12, 64)) == B.SCD_ENOMEM
     assert st.status == B.SCD_ENOMEM
+
+
+def test_sym_workspace_counts_orbit_representatives():
+    # 16x16 lattice, all sources: C4v orbits of 8 (4 on the diagonals) -> 36 representatives
+    p = B.problem(16, 16, 64, 16, 0.1, 10.0)
+    every = list(range(256))
+    full = B.workspace_bytes(p, 256, 256)
+    red = B.sym_workspace_bytes(p, every, 256)
+    assert red < full / 6
+    assert red >= B.workspace_bytes(p, 36, 36)
+    assert red < B.workspace_bytes(p, 37, 37)
+    # 3x5 (C2v): orbits of 4, 2 on the middle row/column, 1 at the centre -> 6
+    q = B.problem(3, 5, 10, 4, 0.1, 2.0)
+    assert B.workspace_bytes(q, 6, 6) <= B.sym_workspace_bytes(q, list(range(15)), 15) \
+        < B.workspace_bytes(q, 7, 7)

@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
                     help="skip the time-to-solution and adjoint legs (profiling runs)")
-    ap.add_argument("--legs", default="fp64,mixed,gmres,adjoint",
-                    help="comma list of extra legs: fp64, mixed, gmres, adjoint")
+    ap.add_argument("--legs", default="fp64,mixed,sym,gmres,adjoint",
+                    help="comma list of extra legs: fp64, mixed, sym, gmres, adjoint")
     ap.add_argument("--gmres-restart", type=int, default=6)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -89,6 +89,24 @@ def cpu_baseline(wl, flops_per_source):
                       f"LU (scipy/OpenBLAS), {secs:.1f} s incl. S build; value = GPU-path "
                       f"algorithmic flops for that source / oracle time",
             "seconds": secs}
+
+
+def orbit_count(Lx, Ly):
+    """Orbits of the lattice sites under the point group about the lattice
+    centre (C4v for a square lattice, else C2v): the sources the point-group
+    legs solve."""
+    seen, n = set(), 0
+    for x in range(Lx):
+        for y in range(Ly):
+            if (x, y) in seen:
+                continue
+            n += 1
+            for mx in (x, Lx - 1 - x):
+                for my in (y, Ly - 1 - y):
+                    seen.add((mx, my))
+                    if Lx == Ly:
+                        seen.add((my, mx))
+    return n
 
 
 def gmres_leg(B, prob, S, V, U, J, src, block, n_ref, restart):
@@ -242,15 +260,24 @@ def main():
                  ("mixed_fp32_tol1e-12", B.PREC_FP32, 1e-12),
                  ("mixed_bf16x3_tol1e-9", B.PREC_BF16X3, 1e-9),
                  ("mixed_bf16x3_tol1e-12", B.PREC_BF16X3, 1e-12))
+    if "sym" in want:
+        legs += (("fp64_pointgroup_tol1e-12", B.PREC_FP64, args.tol),
+                 ("fp64_pointgroup_tol1e-9", B.PREC_FP64, 1e-9),
+                 ("mixed_bf16x3_pointgroup_tol1e-9", B.PREC_BF16X3, 1e-9))
     for label, prec, tol in legs:
-        ws_p = ws if prec == B.PREC_FP64 else torch.empty(
-            B.workspace_bytes(prob, len(src), block, prec), dtype=torch.uint8, device=dev)
+        # point-group legs: one source per C4v orbit (36 of 256), every G_ij kept
+        sym = "pointgroup" in label
+        solve = B.dyson_iterate_sym if sym else B.dyson_iterate
+        need = (B.sym_workspace_bytes(prob, src, block, prec) if sym
+                else B.workspace_bytes(prob, len(src), block, prec))
+        ws_p = ws if (prec == B.PREC_FP64 and not sym) else torch.empty(
+            need, dtype=torch.uint8, device=dev)
         for rep in range(2):          # first repetition warms up
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             B.sigma_build(prob, V, U, S)
-            r = B.dyson_iterate(prob, S, J, src, block_sites=block, prec=prec, tol=tol,
-                                max_iter=1000, ws=ws_p, out=outs)
+            r = solve(prob, S, J, src, block_sites=block, prec=prec, tol=tol,
+                      max_iter=1000, ws=ws_p, out=outs)
             n_p, _ = B.local_observables(prob, r["G_loc"], r["G_nn"], J)
             torch.cuda.synchronize()
             t_p = time.perf_counter() - t1
@@ -262,6 +289,8 @@ def main():
                       "fp64_kernel_ms": round(1e3 * st_p["sweep_kernel_seconds"], 2),
                       "lowp_kernel_ms": round(1e3 * st_p["lowp_kernel_seconds"], 2),
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
+        if sym:
+            tts[label]["sources_solved"] = orbit_count(wl.Lx, wl.Ly)
     if "gmres" in want:
         tts.update(gmres_leg(B, prob, S, V, U, J, src, block, n_ref, args.gmres_restart))
     if tts:

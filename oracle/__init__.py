@@ -25,7 +25,9 @@ What it computes (plain, slow, obviously correct, complex128 throughout):
                      (App. C, the Dyson-series view).
 * ``gmres``       -- preconditioned restarted GMRES per unit-vector column
                      (App. C), the paper's own solver for the same system.
-* ``observables`` -- occupancy and kinetic energy (Sec. III.A).
+* ``observables`` -- occupancy, kinetic energy and double occupancy (Sec. III.A,
+                     eq. docc with the derivative of App. B), the doubly
+                     occupied fraction (Sec. V.B) and dt -> 0 extrapolation.
 * ``gradients``   -- dense adjoint formulas for d(sum_i w_i n_i(t_end)).
 
 Pins (tests/test_oracle_*.py, run with ``-m "not gpu"``) tie every function to
@@ -41,7 +43,8 @@ from .lattice import neighbours, hopping_on_contour, hopping_operator_dense
 from .dyson import (blockdiag, dyson_dense, dyson_columns_blocktri,
                     neumann_partial_sums, dense_system_matrix)
 from .gmres import gmres_column, gmres_dense
-from .observables import occupancy, kinetic_energy
+from .observables import (occupancy, kinetic_energy, double_occupancy,
+                          doubly_occupied_fraction, extrapolate_dt)
 from .gradients import (loss_and_grad_dense, loss_dense, site_levels,
                         atomic_gf_derivatives)
 from .observables import local_blocks_from_dense, neighbour_blocks_from_dense
@@ -52,7 +55,8 @@ __all__ = [
     "neighbours", "hopping_on_contour", "hopping_operator_dense",
     "blockdiag", "dyson_dense", "dyson_columns_blocktri",
     "neumann_partial_sums", "dense_system_matrix", "gmres_column", "gmres_dense",
-    "occupancy", "kinetic_energy", "loss_and_grad_dense", "loss_dense",
+    "occupancy", "kinetic_energy", "double_occupancy", "doubly_occupied_fraction",
+    "extrapolate_dt", "loss_and_grad_dense", "loss_dense",
     "site_levels", "atomic_gf_derivatives",
     "local_blocks_from_dense", "neighbour_blocks_from_dense",
 ]

@@ -44,3 +44,58 @@ def neighbour_blocks_from_dense(G: np.ndarray, n_t: int, nbr: np.ndarray, sites)
             if k >= 0:
                 out[s, d] = G[k * n_t:(k + 1) * n_t, j * n_t:(j + 1) * n_t]
     return out
+
+
+def double_occupancy(G_loc: np.ndarray, G_nn: np.ndarray, nbr_of_src: np.ndarray,
+                     eps_src: np.ndarray, U_real: np.ndarray, J_real: np.ndarray,
+                     c: Contour) -> np.ndarray:
+    """D[s, a] = <n_up n_down>(t_a) of each source site from eq. docc:
+
+        d/dt G_loc(t, t')|_{t' = t^+} = U(t) D(t) + eps n_sigma(t) + e_kin(t),
+
+    the time derivative taken as App. B does, one-sided on the forward branch
+    with t' = t^+ held at the backward point b(a) of the same time:
+    (G[a, b(a)] - G[a-1, b(a)]) / dt for a >= 1, and the forward difference
+    (G[1, b(0)] - G[0, b(0)]) / dt at a = 0.  The real part is used (the
+    imaginary part is O(dt)).  Error O(dt), removed by extrapolation.
+    """
+    if c.n_real < 2:
+        raise ValueError("the derivative needs at least two forward points")
+    a = np.arange(c.n_real)
+    b = c.partner(a)
+    prev = np.where(a >= 1, a - 1, 1)
+    n = occupancy(G_loc, c)
+    ek = kinetic_energy(G_nn, nbr_of_src, J_real, c)
+    U = np.asarray(U_real, dtype=np.float64)
+    out = np.zeros((G_loc.shape[0], c.n_real), dtype=np.float64)
+    for s in range(G_loc.shape[0]):
+        diff = np.where(a >= 1, G_loc[s][a, b] - G_loc[s][prev, b],
+                        G_loc[s][prev, b] - G_loc[s][a, b])
+        dG = np.real(diff) / c.dt
+        out[s] = (dG - eps_src[s] * n[s] - ek[s]) / U
+    return out
+
+
+def doubly_occupied_fraction(D: np.ndarray, n_sigma: np.ndarray) -> np.ndarray:
+    """D~(t) = 2 sum_i D_i(t) / N with N = sum_i n_i(t) = 2 sum_i n_i,sigma(t)
+    (Sec. V.B), over the sites given."""
+    return 2.0 * D.sum(axis=0) / (2.0 * n_sigma.sum(axis=0))
+
+
+def extrapolate_dt(dts, values) -> np.ndarray:
+    """Value at dt -> 0 of the polynomial in dt through the given points (linear
+    for two step sizes, quadratic for three), per entry (Sec. IV.D)."""
+    h = np.asarray(dts, dtype=np.float64)
+    vals = np.asarray(values, dtype=np.float64)
+    if h.ndim != 1 or len(h) not in (2, 3) or vals.shape[0] != len(h):
+        raise ValueError("two or three step sizes, one row of values each")
+    if len(set(h.tolist())) != len(h):
+        raise ValueError("step sizes must differ")
+    out = np.zeros(vals.shape[1:], dtype=np.float64)
+    for k in range(len(h)):
+        wgt = 1.0
+        for j in range(len(h)):
+            if j != k:
+                wgt *= (0.0 - h[j]) / (h[k] - h[j])
+        out = out + wgt * vals[k]
+    return out

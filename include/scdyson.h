@@ -238,6 +238,39 @@ int local_observables(const scd_problem* p, const void* G_loc, const void* G_nn,
                       void* stream);
 
 /*
+ * Double occupancy D_s(t_a) = <n_up n_down> of each source site (Sec. III.A,
+ * eq. docc), from the blocks dyson_iterate returns:
+ *     U(t_a) D = Re dG - eps_j n_s(t_a) - ekin_s(t_a),   j = src[s],
+ * with dG the time derivative of G_loc at equal times taken one-sided as in
+ * App. B, t' = t^+ held at the backward point b(a) of the same time:
+ * (G_loc[s][a][b(a)] - G_loc[s][a-1][b(a)]) / dt for a >= 1 and
+ * (G_loc[s][1][b(0)] - G_loc[s][0][b(0)]) / dt at a = 0, and
+ * eps_j = V_j - U(t_min)/2 - mu.  Discretisation error O(dt) (O(dt^2) for
+ * constant U); combine runs at several dt with scd_extrapolate_dt.
+ *   G_loc, G_nn  device, as local_observables (G_nn required)
+ *   J, U         device double[n_real];  V device double[N_r]
+ *   src          DEVICE int32[n_src]: the site of each block
+ *   d_out        device double[n_src][n_real]
+ *   frac_out     device double[n_real] or NULL: the doubly occupied fraction
+ *                2 sum_s D_s / (2 sum_s n_s) of the listed sites (Sec. V.B)
+ * Needs n_real >= 2; D is Inf/NaN where U(t_a) = 0.
+ */
+int double_occupancy(const scd_problem* p, const void* G_loc, const void* G_nn,
+                     const double* J, const double* V, const double* U,
+                     const int32_t* src, int32_t n_src, double* d_out, double* frac_out,
+                     void* stream);
+
+/*
+ * dt -> 0 extrapolation of results at two or three step sizes (Sec. IV.D:
+ * linear or quadratic in dt): out[i] = value at dt = 0 of the polynomial
+ * through (dts[k], values[k][i]).  Host memory; values sampled at the same
+ * physical times for every dt.  SCD_EINVAL for n_dt not 2 or 3 or equal
+ * step sizes.
+ */
+int scd_extrapolate_dt(const double* dts, int32_t n_dt, const double* values, int32_t n,
+                       double* out);
+
+/*
  * Device workspace (bytes) for dyson_adjoint at precision prec.
  */
 int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* bytes);

@@ -962,6 +962,48 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
 
 }  // namespace
 
+int double_occupancy(const scd_problem* p, const void* G_loc, const void* G_nn, const double* J,
+                     const double* V, const double* U, const int32_t* src, int32_t n_src,
+                     double* d_out, double* frac_out, void* stream) {
+    Geom g;
+    int rc = check_problem(p, 1 << 20, &g);
+    if (rc) return rc;
+    if (n_src < 1) return fail(SCD_EINVAL, "n_src must be >= 1");
+    if (g.n_real < 2) return fail(SCD_EINVAL, "the time derivative needs n_real >= 2");
+    if (!G_loc || !G_nn || !J || !V || !U || !src || !d_out)
+        return fail(SCD_EINVAL, "G_loc, G_nn, J, V, U, src and d_out must be non-NULL");
+    hipStream_t st = (hipStream_t)stream;
+    SCD_HIP(launch_docc(g, (const double2*)G_loc, (const double2*)G_nn, J, V, U, src, n_src, d_out,
+                        frac_out, st),
+            "double_occupancy launch");
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int scd_extrapolate_dt(const double* dts, int32_t n_dt, const double* values, int32_t n,
+                       double* out) {
+    if (!dts || !values || !out) return fail(SCD_EINVAL, "dts, values and out must be non-NULL");
+    if (n_dt != 2 && n_dt != 3) return fail(SCD_EINVAL, "two or three step sizes");
+    if (n < 0) return fail(SCD_EINVAL, "n must be >= 0");
+    for (int k = 0; k < n_dt; ++k)
+        for (int j = 0; j < k; ++j)
+            if (!(dts[k] != dts[j])) return fail(SCD_EINVAL, "step sizes must differ");
+    // Lagrange weights of the interpolating polynomial at dt = 0.
+    double w[3];
+    for (int k = 0; k < n_dt; ++k) {
+        w[k] = 1.0;
+        for (int j = 0; j < n_dt; ++j)
+            if (j != k) w[k] *= (0.0 - dts[j]) / (dts[k] - dts[j]);
+    }
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int k = 0; k < n_dt; ++k) v += w[k] * values[(size_t)k * n + i];
+        out[i] = v;
+    }
+    g_last_error.clear();
+    return SCD_OK;
+}
+
 int dyson_iterate(const scd_problem* p, const void* S, const double* J, const int32_t* src,
                   int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
                   void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,

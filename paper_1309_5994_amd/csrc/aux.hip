@@ -177,6 +177,49 @@ void observables_kernel(const double2* __restrict__ G_loc, const double2* __rest
     }
 }
 
+// Double occupancy D_s(t_a) of source site j = src[s] from eq. docc:
+//   U(t_a) D = Re dG - eps_j n_s(t_a) - ekin_s(t_a),
+// dG the one-sided time derivative of G_loc at equal times (App. B), t' = t^+
+// held at the backward point b(a):  (G[a][b] - G[a-1][b]) / dt for a >= 1,
+// (G[1][b] - G[0][b]) / dt at a = 0; eps_j = V_j - U(t_min)/2 - mu.
+__global__ __launch_bounds__(256)
+void docc_kernel(const double2* __restrict__ G_loc, const double2* __restrict__ G_nn,
+                 const double* __restrict__ J, const double* __restrict__ V,
+                 const double* __restrict__ U, const int* __restrict__ src, int n_src,
+                 double* __restrict__ d_out, Geom g) {
+    const int n_t = g.n_t, n_real = g.n_real;
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_src * n_real) return;
+    const int s = e / n_real, a = e - (e / n_real) * n_real;
+    const int b = 2 * n_real - 1 - a;
+    const int prev = a >= 1 ? a - 1 : 1;
+    const double2* Gs = G_loc + (size_t)s * n_t * n_t;
+    const double2 gab = Gs[(size_t)a * n_t + b];
+    const double2 gpb = Gs[(size_t)prev * n_t + b];
+    const double dG = (a >= 1 ? gab.x - gpb.x : gpb.x - gab.x) / g.dt;
+    double im = 0.0;
+    for (int d = 0; d < 4; ++d) im += G_nn[(((size_t)s * 4 + d) * n_t + a) * n_t + b].y;
+    const double ekin = -J[a] * im;
+    const double eps = V[src[s]] - 0.5 * U[0] - g.mu;
+    d_out[e] = (dG - eps * gab.y - ekin) / U[a];
+}
+
+// D~(t_a) = 2 sum_s D_s / (2 sum_s n_s): the doubly occupied fraction of the
+// listed sites (one thread per time, sources summed in order).
+__global__ __launch_bounds__(256)
+void docc_fraction_kernel(const double2* __restrict__ G_loc, const double* __restrict__ d,
+                          int n_src, double* __restrict__ frac, Geom g) {
+    const int a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= g.n_real) return;
+    const int n_t = g.n_t, b = 2 * g.n_real - 1 - a;
+    double sd = 0.0, sn = 0.0;
+    for (int s = 0; s < n_src; ++s) {
+        sd += d[(size_t)s * g.n_real + a];
+        sn += G_loc[((size_t)s * n_t + a) * n_t + b].y;
+    }
+    frac[a] = sd / sn;
+}
+
 // Elementwise helpers of mixed-precision refinement.
 __global__ __launch_bounds__(256)
 void to_f32_kernel(const dvec2* __restrict__ in, fvec2* __restrict__ out, size_t n) {
@@ -254,6 +297,18 @@ hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* s
                           hipStream_t st) {
     hipLaunchKernelGGL(extract_kernel, dim3(4096), dim3(256), 0, st, X, ldx, src_blk, bs,
                        blk_start, n_src, G_cols, G_loc, G_nn, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_docc(const Geom& g, const double2* G_loc, const double2* G_nn, const double* J,
+                       const double* V, const double* U, const int* src, int n_src, double* d_out,
+                       double* frac_out, hipStream_t st) {
+    const int total = n_src * g.n_real;
+    hipLaunchKernelGGL(docc_kernel, dim3((total + 255) / 256), dim3(256), 0, st, G_loc, G_nn, J, V,
+                       U, src, n_src, d_out, g);
+    if (frac_out)
+        hipLaunchKernelGGL(docc_fraction_kernel, dim3((g.n_real + 255) / 256), dim3(256), 0, st,
+                           G_loc, d_out, n_src, frac_out, g);
     return hipGetLastError();
 }
 

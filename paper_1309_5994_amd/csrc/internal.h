@@ -216,6 +216,9 @@ hipError_t launch_reduce_max3(const double* partial, int n, unsigned long long* 
 hipError_t launch_extract(const Geom& g, const double2* X, int ldx, const int* src_blk, int bs,
                           int blk_start, int n_src, double2* G_cols, double2* G_loc, double2* G_nn,
                           hipStream_t st);
+hipError_t launch_docc(const Geom& g, const double2* G_loc, const double2* G_nn, const double* J,
+                       const double* V, const double* U, const int* src, int n_src, double* d_out,
+                       double* frac_out, hipStream_t st);
 hipError_t launch_observables(const Geom& g, const double2* G_loc, const double2* G_nn,
                               const double* J, int n_src, double* n_out, double* ekin_out,
                               hipStream_t st);

@@ -98,6 +98,12 @@ def lib():
     L.dyson_gmres.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                               _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.double_occupancy.restype = ctypes.c_int
+    L.double_occupancy.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
+                                   _vp, _vp, _vp]
+    L.scd_extrapolate_dt.restype = ctypes.c_int
+    L.scd_extrapolate_dt.argtypes = [_P(ctypes.c_double), ctypes.c_int32, _P(ctypes.c_double),
+                                     ctypes.c_int32, _P(ctypes.c_double)]
     L.local_observables.restype = ctypes.c_int
     L.local_observables.argtypes = [_P(Problem), _vp, _vp, _vp, ctypes.c_int32, _vp, _vp, _vp]
     L.scd_adjoint_workspace_bytes.restype = ctypes.c_int
@@ -313,6 +319,43 @@ def local_observables(prob: Problem, G_loc, G_nn, J, want_ekin=True, stream=None
     _check(lib().local_observables(ctypes.byref(prob), _ptr(G_loc), _ptr(G_nn if want_ekin else None),
                                    _ptr(J), n_src, _ptr(n), _ptr(ekin), _stream(stream)))
     return n, ekin
+
+
+def double_occupancy(prob: Problem, G_loc, G_nn, J, V, U, src, want_fraction=True,
+                     stream=None):
+    """(D [n_src, n_real], doubly occupied fraction [n_real] or None) on the device
+    for the source sites ``src`` of the blocks (eq. docc)."""
+    import torch
+    n_src = int(G_loc.shape[0])
+    _need(G_loc, torch.complex128, (n_src, prob.n_t, prob.n_t), "G_loc")
+    _need(G_nn, torch.complex128, (n_src, 4, prob.n_t, prob.n_t), "G_nn")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    _need(U, torch.float64, (prob.n_real,), "U")
+    _need(V, torch.float64, (prob.n_r,), "V")
+    src_d = torch.as_tensor(np.asarray(src, dtype=np.int32).reshape(-1), device=G_loc.device)
+    if src_d.numel() != n_src:
+        raise ValueError("one source site per block")
+    D = torch.empty((n_src, prob.n_real), dtype=torch.float64, device=G_loc.device)
+    frac = torch.empty(prob.n_real, dtype=torch.float64, device=G_loc.device) if want_fraction \
+        else None
+    _check(lib().double_occupancy(ctypes.byref(prob), _ptr(G_loc), _ptr(G_nn), _ptr(J), _ptr(V),
+                                  _ptr(U), _ptr(src_d), n_src, _ptr(D), _ptr(frac),
+                                  _stream(stream)))
+    return D, frac
+
+
+def extrapolate_dt(dts, values):
+    """Value at dt -> 0 (linear for two step sizes, quadratic for three) of host
+    arrays values[k] sampled at the same physical times."""
+    dts = np.ascontiguousarray(np.asarray(dts, dtype=np.float64))
+    vals = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+    shape = vals.shape[1:]
+    flat = vals.reshape(len(dts), -1)
+    out = np.empty(flat.shape[1], dtype=np.float64)
+    _check(lib().scd_extrapolate_dt(dts.ctypes.data_as(_P(ctypes.c_double)), int(dts.size),
+                                    flat.ctypes.data_as(_P(ctypes.c_double)), int(flat.shape[1]),
+                                    out.ctypes.data_as(_P(ctypes.c_double))))
+    return out.reshape(shape)
 
 
 def adjoint_workspace_bytes(prob: Problem, prec=PREC_FP64) -> int:

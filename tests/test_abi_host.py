@@ -124,3 +124,17 @@ def test_sym_workspace_counts_orbit_representatives():
     q = B.problem(3, 5, 10, 4, 0.1, 2.0)
     assert B.workspace_bytes(q, 6, 6) <= B.sym_workspace_bytes(q, list(range(15)), 15) \
         < B.workspace_bytes(q, 7, 7)
+
+
+def test_extrapolation_matches_the_oracle_and_validates():
+    import oracle as O
+    rng = np.random.default_rng(11)
+    vals = rng.standard_normal((3, 7))
+    for dts in ([0.1, 0.05, 0.025], [0.2, 0.1]):
+        got = B.extrapolate_dt(dts, vals[:len(dts)])
+        ref = O.extrapolate_dt(dts, vals[:len(dts)])
+        assert np.abs(got - ref).max() <= 1e-14 * max(1.0, np.abs(ref).max())
+    with pytest.raises(B.ScdError):
+        B.extrapolate_dt([0.1, 0.1], vals[:2])
+    with pytest.raises(B.ScdError):
+        B.extrapolate_dt([0.1], vals[:1])

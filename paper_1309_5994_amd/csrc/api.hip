@@ -201,7 +201,7 @@ struct GmBufs {
     double2* gv;         // [kMaxBasis + 1][ldx]
     double2* y;          // [kMaxBasis][ldx]
     double* x0n;         // [ldx]
-    int rows, ldx, nch;
+    int rows, ldx, nch, chunk_rows;
 };
 
 // Host side of the sweep loops of one column block.
@@ -468,14 +468,48 @@ struct Solver {
         return code;
     }
 
+    // Elements (row x column) of the streaming passes' workgroups whose
+    // nearest (site, source) pair lies within lattice distance d, cumulative
+    // in d: the part of a Krylov vector a pass with light-cone radius d moves.
+    std::vector<double> gs_area;
+    void gs_area_table(const GsPass& p, const int32_t* src_host) {
+        gs_area.assign(g.Lx + g.Ly + 2, 0.0);
+        const int spc = p.chunk_rows / g.mp;
+        for (int c_lo = 0; c_lo < p.ldx; c_lo += 64) {
+            const int c_hi = std::min(p.ldx, c_lo + 64) - 1;
+            const int s_lo = c_lo / g.n_t, s_hi = std::min(c_hi / g.n_t, p.bs - 1);
+            if (s_lo >= p.bs) continue;
+            for (int i_lo = 0; i_lo < g.n_r; i_lo += spc) {
+                const int i_hi = std::min(g.n_r, i_lo + spc) - 1;
+                int dmin = 1 << 30;
+                for (int s = s_lo; s <= s_hi; ++s) {
+                    const int j = src_host[s];
+                    for (int i = i_lo; i <= i_hi; ++i) {
+                        int dx = std::abs(i / g.Ly - j / g.Ly), dy = std::abs(i % g.Ly - j % g.Ly);
+                        if (g.periodic) {
+                            dx = std::min(dx, g.Lx - dx);
+                            dy = std::min(dy, g.Ly - dy);
+                        }
+                        dmin = std::min(dmin, dx + dy);
+                    }
+                }
+                gs_area[std::min<int>(dmin, (int)gs_area.size() - 1)] +=
+                    (double)(i_hi - i_lo + 1) * g.mp * (c_hi - c_lo + 1);
+            }
+        }
+        for (size_t d = 1; d < gs_area.size(); ++d) gs_area[d] += gs_area[d - 1];
+    }
+
     // One streaming pass, timed and counted; `vectors` = Krylov-sized vectors
-    // it reads plus writes.
+    // it reads plus writes, over the workgroups inside its light cone.
     int gs(int mode, GsPass p, int vectors) {
         SCD_HIP(ts.mark(st), "event record");
         SCD_HIP(launch_gs(mode, p, st), "Gram-Schmidt launch");
         SCD_HIP(ts.mark(st), "event record");
         stats->stream_launches++;
-        stats->stream_bytes += (double)vectors * p.rows * (double)p.ldx * sizeof(double2);
+        const double area = p.radius < 0 ? (double)p.rows * p.ldx
+                                         : gs_area[std::min<size_t>(p.radius, gs_area.size() - 1)];
+        stats->stream_bytes += (double)vectors * area * sizeof(double2);
         return SCD_OK;
     }
 
@@ -488,8 +522,8 @@ struct Solver {
     // once the largest rotated residual |g_{d+1}| / |X0| over the columns is at
     // most tol; the block has converged when the recomputed FP64 residual
     // |z| / |X0| of every column is at most tol.
-    int solve_gmres(SweepArgs a, const int* src_blk, const GmBufs& b, int restart, double tol,
-                    int max_iter, BlockResult* res) {
+    int solve_gmres(SweepArgs a, const int* src_blk, const int32_t* src_host, const GmBufs& b,
+                    int restart, double tol, int max_iter, BlockResult* res) {
         const int cps = g.n_t;
         const bool cone = a.lc_sweep >= 0;
         const size_t vbytes = (size_t)b.rows * b.ldx * sizeof(double2);
@@ -500,8 +534,17 @@ struct Solver {
         p.sig = b.sig;
         p.rows = b.rows;
         p.ldx = b.ldx;
-        p.chunk_rows = (b.rows + b.nch - 1) / b.nch;
+        p.chunk_rows = b.chunk_rows;
         p.pnorm = b.pn;
+        p.src_blk = src_blk;
+        p.radius = -1;
+        p.bs = a.bs;
+        p.n_t = g.n_t;
+        p.mp = g.mp;
+        p.Lx = g.Lx;
+        p.Ly = g.Ly;
+        p.periodic = g.periodic;
+        gs_area_table(p, src_host);
         const size_t pstride = (size_t)kMaxBasis * b.ldx;
         GivensArgs ga{};
         ga.pa = b.pa;
@@ -522,6 +565,7 @@ struct Solver {
             GsPass q = p;
             q.k = 0;
             q.w = b.u;
+            q.radius = cone ? 0 : -1;
             if (gs(GS_NORM, q, 1)) return SCD_EHIP;
             SCD_HIP(launch_colnorm(b.pn, b.nch, b.ldx, b.x0n, st), "column norm launch");
         }
@@ -557,6 +601,7 @@ struct Solver {
                 GsPass q = p;
                 q.k = 0;
                 q.w = b.Q;
+                q.radius = cone ? radius_u + 1 : -1;
                 if (gs(GS_NORM, q, 1)) return SCD_EHIP;
             }
             ga.d = -1;
@@ -593,6 +638,7 @@ struct Solver {
                 GsPass q = p;
                 q.k = k;
                 q.w = w;
+                q.radius = cone ? radius_u + 2 + d : -1;   // w reaches one hop beyond v_d
                 q.wsig = b.sig + (size_t)d * b.ldx;     // T q_d = sig_d T v_d
                 q.pdot = b.pa;
                 if (gs(GS_DOTS, q, k + 1)) return SCD_EHIP;          // h1
@@ -622,6 +668,7 @@ struct Solver {
                     GsPass uq = p;
                     uq.k = k;
                     uq.w = b.u;
+                    uq.radius = cone ? radius_u + 1 + d : -1;
                     uq.coef = b.y;
                     uq.coef_parts = 1;
                     uq.coef_pstride = 0;
@@ -1050,7 +1097,7 @@ int scd_sym_workspace_bytes(const scd_problem* p, const int32_t* src, int32_t n_
 namespace {
 
 struct GmLayout {
-    int ldx, ntn, nwg, nch, rows;
+    int ldx, ntn, nwg, nch, rows, chunk_rows;
     size_t off_st, off_u, off_q, qstride_bytes, off_pa, off_pb, off_pn, off_sig, off_R, off_cs,
         off_sn, off_g, off_y, off_x0n, off_partial, off_slot, off_src, off_order, total;
 };
@@ -1065,7 +1112,11 @@ GmLayout gm_layout(const Geom& g, int n_src, int block_sites, int restart) {
     L.ntn = L.ldx / kColsPerWG;
     L.nwg = g.n_r * L.ntn;
     L.rows = g.n_r * g.mp;
-    L.nch = gs_chunks(L.rows, L.ldx);
+    // Row chunks of whole sites (the passes skip chunks outside the light
+    // cone); nch is exactly the number of chunks a pass launches.
+    const int spc = (g.n_r + gs_chunks(L.rows, L.ldx) - 1) / gs_chunks(L.rows, L.ldx);
+    L.nch = (g.n_r + spc - 1) / spc;
+    L.chunk_rows = spc * g.mp;
     const size_t it64 = (size_t)L.rows * L.ldx * sizeof(double2);
     const size_t col = (size_t)L.ldx;
     size_t off = 0;
@@ -1188,6 +1239,7 @@ int dyson_gmres(const scd_problem* p, const void* S, const double* J, const int3
     b.rows = L.rows;
     b.ldx = L.ldx;
     b.nch = L.nch;
+    b.chunk_rows = L.chunk_rows;
 
     const int bs_max = block_sites < n_src ? block_sites : n_src;
     double worst_err = 0.0, worst_rho = 0.0;
@@ -1217,7 +1269,8 @@ int dyson_gmres(const scd_problem* p, const void* S, const double* J, const int3
                                   nullptr, st),
                 "init_block launch");
         BlockResult res;
-        const int code = sv.solve_gmres(a, src_blk, b, restart, tol, max_iter, &res);
+        const int code = sv.solve_gmres(a, src_blk, src + blk_start, b, restart, tol, max_iter,
+                                        &res);
         if (code == SCD_EHIP) return finish(code);
         if (code == SCD_ENOTCONV)
             fail(SCD_ENOTCONV, "block at source %d not converged after %d GMRES steps (e=%g)",

@@ -77,8 +77,31 @@ void gs_kernel(GsPass p) {
     for (int i = 0; i < KB; ++i) acc[i] = dvec2{0.0, 0.0};
     double nrm = 0.0;
 
-    const int r0 = blockIdx.y * p.chunk_rows;
-    const int r1 = min(p.rows, r0 + p.chunk_rows);
+    int r0 = blockIdx.y * p.chunk_rows;
+    int r1 = min(p.rows, r0 + p.chunk_rows);
+    if (p.radius >= 0) {
+        // Workgroup-uniform: nearest (site of the chunk, source of the strip) pair.
+        const int c_lo = blockIdx.x * kGsCols;
+        const int s_lo = c_lo / p.n_t;
+        const int s_hi = min((c_lo + kGsCols - 1) / p.n_t, p.bs - 1);
+        const int i_lo = r0 / p.mp, i_hi = (r1 - 1) / p.mp;
+        int dmin = 1 << 30;
+        for (int s = s_lo; s <= s_hi; ++s) {
+            const int j = p.src_blk[s];
+            const int xj = j / p.Ly, yj = j - (j / p.Ly) * p.Ly;
+            for (int i = i_lo; i <= i_hi; ++i) {
+                const int xi = i / p.Ly, yi = i - (i / p.Ly) * p.Ly;
+                int dx = xi > xj ? xi - xj : xj - xi;
+                int dy = yi > yj ? yi - yj : yj - yi;
+                if (p.periodic) {
+                    dx = min(dx, p.Lx - dx);
+                    dy = min(dy, p.Ly - dy);
+                }
+                dmin = min(dmin, dx + dy);
+            }
+        }
+        if (s_lo >= p.bs || dmin > p.radius) r1 = r0;    // all rows zero: partials only
+    }
     for (int r = r0 + wv; r < r1; r += 4) {
         const size_t off = (size_t)r * p.ldx + cc;
         dvec2 x = __builtin_nontemporal_load(&w[off]) * ws;
@@ -295,7 +318,7 @@ hipError_t launch_gs_kb(int mode, const GsPass& p, dim3 grid, hipStream_t st) {
 
 int gs_chunks(int rows, int ldx) {
     const int strips = (ldx + kGsCols - 1) / kGsCols;
-    int nch = (4096 + strips - 1) / strips;
+    int nch = (16384 + strips - 1) / strips;
     const int cap = (rows + 63) / 64;
     if (nch > cap) nch = cap;
     if (nch > 64) nch = 64;

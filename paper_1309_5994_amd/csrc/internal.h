@@ -181,7 +181,12 @@ struct GsPass {
     size_t coef_pstride;  // elements between parts
     double2* pdot;        // DOTS: [chunk][kMaxBasis][ldx] partial <q_i, x>
     double* pnorm;        // NORM: [chunk][ldx] partial |x|^2
-    int rows, ldx, chunk_rows;
+    int rows, ldx, chunk_rows;   // chunk_rows: a multiple of mp (whole sites)
+    // Light cone: every vector of the pass vanishes on sites farther than
+    // `radius` from the source of a column; a workgroup whose sites and
+    // sources are all farther apart skips its rows (radius < 0: no skipping).
+    const int* src_blk;
+    int radius, bs, n_t, mp, Lx, Ly, periodic;
 };
 // Per-column Hessenberg / Givens state of one Arnoldi step d (d < 0: cycle start).
 struct GivensArgs {

@@ -249,6 +249,17 @@ def main():
     }
     # Time to a converged G at the densities' 1e-8 bar, FP64 vs mixed precision;
     # errors are measured against the FP64 run at 1e-12 above.
+    # Double occupancy and doubly occupied fraction (eq. docc) of all 256 sites
+    # from the step's blocks.
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        D, frac = B.double_occupancy(prob, outs["G_loc"], outs["G_nn"], J, V, U, src)
+        torch.cuda.synchronize()
+        t_d = time.perf_counter() - t1
+    rec["double_occupancy"] = {"ms": round(1e3 * t_d, 3),
+                               "fraction_t0": float(frac[0]),
+                               "fraction_t_end": float(frac[-1])}
     n_ref = n.clone()
     tts = {}
     want = set() if args.quick else set(args.legs.split(","))

@@ -225,7 +225,10 @@ int dyson_gmres(const scd_problem* p, const void* S, const double* J, const int3
 /*
  * Local observables of Sec. III.A from the blocks dyson_iterate returns.
  *   n_s(t_a)     = Im G_loc[s][a][b(a)]                    (occupancy per spin)
- *   ekin_s(t_a)  = Re( i sum_d J(t_a) G_nn[s][d][a][b(a)] ) (kinetic energy per spin)
+ *   ekin_s(t_a)  = Re(-i sum_d J(t_a) G_nn[s][d][a][b(a)] ) (kinetic energy per spin:
+ *                  the expectation of the site's hopping terms; G is the propagator of
+ *                  hopping +J, the gauge image of eq. model's -J, so Sec. III.A's
+ *                  +i sum J G with the Hamiltonian's amplitude reads -i sum J G here)
  * for forward points a in [0, n_real), b(a) = 2 n_real - 1 - a.
  *   G_loc  device complex128[n_src][N_t][N_t]
  *   G_nn   device complex128[n_src][4][N_t][N_t] (may be NULL if ekin_out is NULL)

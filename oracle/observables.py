@@ -3,8 +3,14 @@
 Paper: Sec. III.A.  The spin-sigma occupancy is -i G_loc(t, t + 0^+); on the
 contour grid t + 0^+ is the backward point at the same physical time, so
 n_i(t_a) = Re(-i G[(i,a), (i,b(a))]) = Im G[(i,a), (i,b(a))].  The kinetic
-energy of site i is +i sum_{j NN of i} J(t) G(r_j, t; r_i, t), read at the same
-pair of contour points.  Values are per spin; the paramagnetic total is twice.
+energy of site i is the expectation of its hopping terms, sum_j h_ij
+<c_i^dag c_j>(t) = -i sum_j h_ij G(r_j, t; r_i, t^+), read at the same pair of
+contour points.  The G solved here (eq. Glatt with +J, G = S + S D G) is the
+propagator of hopping h_ij = +J (the U = 0 pin fixes this), the gauge image
+c_i -> (-1)^(x+y) c_i of the Hamiltonian's -J c^dag c (eq. model); Sec. III.A
+writes +i sum_j J G with the Hamiltonian's amplitude, so on this G the same
+physical quantity is -i sum_j J G.  Values are per spin; the paramagnetic total
+is twice.
 """
 import numpy as np
 
@@ -19,7 +25,8 @@ def occupancy(G_loc: np.ndarray, c: Contour) -> np.ndarray:
 
 def kinetic_energy(G_nn: np.ndarray, nbr_of_src: np.ndarray, J_real: np.ndarray,
                    c: Contour) -> np.ndarray:
-    """e_kin[s, a] from G_nn[s, d] = G(neighbour d of source s, source s) blocks."""
+    """e_kin[s, a] = Re(-i J(t_a) sum_d G_nn[s, d][a, b(a)]) from the blocks
+    G_nn[s, d] = G(neighbour d of source s, source s)."""
     a = np.arange(c.n_real)
     out = np.zeros((G_nn.shape[0], c.n_real), dtype=np.float64)
     for s in range(G_nn.shape[0]):
@@ -28,7 +35,7 @@ def kinetic_energy(G_nn: np.ndarray, nbr_of_src: np.ndarray, J_real: np.ndarray,
             if nbr_of_src[s, d] < 0:
                 continue
             acc += np.asarray(J_real) * G_nn[s, d][a, c.partner(a)]
-        out[s] = np.real(1j * acc)
+        out[s] = np.real(-1j * acc)
     return out
 
 

@@ -158,7 +158,8 @@ void extract_kernel(const double2* __restrict__ X, int ldx, const int* __restric
     }
 }
 
-// n_s(t_a) = Im G_loc[s][a][b(a)], ekin_s(t_a) = Re(i J(t_a) sum_d G_nn[s][d][a][b(a)]).
+// n_s(t_a) = Im G_loc[s][a][b(a)]; ekin_s(t_a) = Re(-i J(t_a) sum_d G_nn[s][d][a][b(a)]),
+// the expectation of the site's hopping terms for the +J hopping G is solved with.
 __global__ __launch_bounds__(256)
 void observables_kernel(const double2* __restrict__ G_loc, const double2* __restrict__ G_nn,
                         const double* __restrict__ J, int n_src, double* __restrict__ n_out,
@@ -172,8 +173,8 @@ void observables_kernel(const double2* __restrict__ G_loc, const double2* __rest
     if (ekin_out) {
         double im = 0.0;
         for (int d = 0; d < 4; ++d) im += G_nn[(((size_t)s * 4 + d) * n_t + a) * n_t + b].y;
-        // Re(i J (x + i y)) = -J y
-        ekin_out[e] = -J[a] * im;
+        // Re(-i J (x + i y)) = J y
+        ekin_out[e] = J[a] * im;
     }
 }
 
@@ -199,7 +200,7 @@ void docc_kernel(const double2* __restrict__ G_loc, const double2* __restrict__ 
     const double dG = (a >= 1 ? gab.x - gpb.x : gpb.x - gab.x) / g.dt;
     double im = 0.0;
     for (int d = 0; d < 4; ++d) im += G_nn[(((size_t)s * 4 + d) * n_t + a) * n_t + b].y;
-    const double ekin = -J[a] * im;
+    const double ekin = J[a] * im;
     const double eps = V[src[s]] - 0.5 * U[0] - g.mu;
     d_out[e] = (dG - eps * gab.y - ekin) / U[a];
 }

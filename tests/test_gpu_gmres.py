@@ -156,3 +156,32 @@ def test_gmres_config2_full_block_sampled_columns(device):
         got = G_loc[s][gold["loc_a"][s], gold["loc_b"][s]]
         assert np.abs(got - ref).max() <= 1e-11 * gmax, s
     assert r["stats"]["status"] == 0
+
+
+def test_gmres_config3_sampled_sources_against_golden(device):
+    """The 24x24 trap with N_t = 176 (Jacobi rate 0.62): the stored oracle
+    sources in one block, GMRES(8), against the stored column samples."""
+    import os
+    import torch
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "cfg3.npz"))
+    wl = W.config(3)
+    src = [int(s) for s in gold["sources"]]
+    B = _B()
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = B.sigma_build(prob, V, U)
+    r = B.dyson_gmres(prob, S, J, src, block_sites=len(src), restart=8, tol=1e-13,
+                      max_iter=300, want_cols=True)
+    n, ek = B.local_observables(prob, r["G_loc"], r["G_nn"], J)
+    assert np.abs(_np(n) - gold["n"]).max() <= 1e-11
+    assert np.abs(_np(ek) - gold["ekin"]).max() <= 1e-11
+    gmax = gold["G_absmax"][0]
+    cols = r["G_cols"]
+    n_t = wl.n_t
+    for s in range(len(src)):
+        site = torch.as_tensor(gold["sample_site"][s], device=cols.device)
+        a = torch.as_tensor(gold["sample_a"][s], device=cols.device)
+        b = torch.as_tensor(gold["sample_b"][s] + s * n_t, device=cols.device)
+        got = _np(cols[site, a, b])
+        exp = gold["sample_re"][s] + 1j * gold["sample_im"][s]
+        assert np.abs(got - exp).max() <= 1e-11 * gmax, s
+    assert r["stats"]["status"] == 0

@@ -99,3 +99,18 @@ def test_sym_config2_all_sources_against_golden(device):
         got = G_loc[s][gold["loc_a"][k], gold["loc_b"][k]]
         assert np.abs(got - ref).max() <= 1e-12 * gmax, s
     assert r["ws"].numel() < B.workspace_bytes(prob, 256, 256) / 6
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+def test_sym_mixed_precision_matches_dense_oracle(prec, device):
+    """Point-group reduction with FP32 / BF16x3 correction sweeps (refined to
+    tol = 1e-13): G to 1e-10 relative, densities to 1e-8."""
+    wl = W.custom(6, 6, 8, 6, J0=0.1)
+    c, S_ref, G = oracle_dense(wl)
+    sources = list(range(wl.n_r))
+    prob, out, n, ek = _sym(wl, device, sources, 4, prec=prec)
+    cols_ref = dense_columns(G, wl.n_r, c.n_t, sources)
+    assert rel_maxnorm(_np(out["G_cols"]), cols_ref) <= 1e-10
+    G_loc = O.local_blocks_from_dense(G, c.n_t, sources)
+    assert np.abs(n - O.occupancy(G_loc, c)).max() <= 1e-8
+    assert out["stats"]["lowp_sweeps"] > 0

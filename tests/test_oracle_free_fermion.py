@@ -104,3 +104,36 @@ def test_free_fermion_periodic_lattice():
     errs = [_run(dt, m, Lx=3, Ly=3, periodic=True, V=np.linspace(-0.2, 0.2, 9), J=0.15)
             for dt, m in GRIDS[:2]]
     assert 1.8 < errs[0][0] / errs[1][0] < 2.3
+
+
+def _ekin_errors(dt, n_imag, T=1.0, beta=2.0, J=0.2, Lx=2, Ly=2, V=(0.1, -0.2, 0.3, 0.0)):
+    """Kinetic energy of each site (Sec. III.A) at U = 0 against the free value
+    sum_j h_ij <c_i^dag c_j> = (h_hop f(h))_ii, constant in time for a
+    time-independent h; returns (max error, the exact values)."""
+    n_real = int(round(T / dt)) + 1
+    c = O.make_contour(n_real, n_imag, dt, beta)
+    V = np.asarray(V)
+    S = np.stack([O.atomic_gf(v, np.zeros(n_real), c) for v in V])
+    Jr = np.full(n_real, J)
+    G = O.dyson_dense(S, O.hopping_operator_dense(Lx, Ly, False, Jr, c))
+    nbr = O.neighbours(Lx, Ly, False)
+    sites = list(range(Lx * Ly))
+    ek = O.kinetic_energy(O.neighbour_blocks_from_dense(G, c.n_t, nbr, sites), nbr, Jr, c)
+    hop = np.zeros((Lx * Ly, Lx * Ly))
+    for i in sites:
+        for k in nbr[i]:
+            if k >= 0:
+                hop[i, k] = J
+    e, vec = np.linalg.eigh(np.diag(V) + hop)
+    f = (vec * (1.0 / (1.0 + np.exp(beta * e)))[None, :]) @ vec.T
+    exact = np.diag(hop @ f)
+    return np.abs(ek - exact[:, None]).max(), exact
+
+
+def test_free_fermion_kinetic_energy_sign_and_convergence():
+    errs = [_ekin_errors(dt, m) for dt, m in GRIDS]
+    exact = errs[0][1]
+    assert np.all(exact < 0)                    # hopping lowers the energy
+    for (e0, _), (e1, _) in zip(errs, errs[1:]):
+        assert 1.7 < e0 / e1 < 2.4
+    assert errs[-1][0] < 0.05 * np.abs(exact).min()

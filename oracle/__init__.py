@@ -25,6 +25,9 @@ What it computes (plain, slow, obviously correct, complex128 throughout):
                      (App. C, the Dyson-series view).
 * ``gmres``       -- preconditioned restarted GMRES per unit-vector column
                      (App. C), the paper's own solver for the same system.
+* ``selfenergy``  -- the second-order strong-coupling self-energy (Sec. III):
+                     Fock-space two-particle propagator, cumulant, Sigma~,
+                     dressed blocks and the mixed self-consistency loop.
 * ``observables`` -- occupancy, kinetic energy and double occupancy (Sec. III.A,
                      eq. docc with the derivative of App. B), the doubly
                      occupied fraction (Sec. V.B) and dt -> 0 extrapolation.
@@ -43,6 +46,7 @@ from .lattice import neighbours, hopping_on_contour, hopping_operator_dense
 from .dyson import (blockdiag, dyson_dense, dyson_columns_blocktri,
                     neumann_partial_sums, dense_system_matrix)
 from .gmres import gmres_column, gmres_dense
+from . import selfenergy
 from .observables import (occupancy, kinetic_energy, double_occupancy,
                           doubly_occupied_fraction, extrapolate_dt)
 from .gradients import (loss_and_grad_dense, loss_dense, site_levels,

@@ -274,6 +274,47 @@ int scd_extrapolate_dt(const double* dts, int32_t n_dt, const double* values, in
                        double* out);
 
 /*
+ * Device workspace (bytes) of sigma2_build and sigma2_dress.
+ */
+int scd_sigma2_workspace_bytes(const scd_problem* p, size_t* bytes);
+
+/*
+ * Second-order strong-coupling self-energy of every site (Sec. III,
+ * eq. defnSigmatilde), paramagnetic:
+ *   Sigma~_i(a, b) = - sum_{s1 = up, dn} sum_{c, d} G~_{up s1}(a, d; c, b) K_i(c, d),
+ *   K_i(c, d) = w_c J(z_c) [sum_{k in nbr(i)} G_loc,k(c, d)] J(z_d) w_d,
+ * with the cumulant G~_{s s1}(t1, t2; t1', t2') = G^II + G(t1,t1') G(t2,t2') delta_{s s1}
+ * - G(t1,t2') G(t2,t1') of the on-site two-particle propagator
+ * G^II = (-i)^2 <T_C c_s(t1) c_s1(t2) c^dag_s1(t1') c^dag_s(t2')>, evaluated on the fly in
+ * the number basis from the tabulated phases (eq. cumulanttabulation) and the
+ * Boltzmann weights at t_min; G = S_i.  At equal contour indices creation operators
+ * count as later than annihilation operators.
+ *   V, U, J     device double[N_r], [n_real], [n_real] (as sigma_build / dyson_iterate)
+ *   S           device complex128[N_r][N_t][N_t] from sigma_build
+ *   G_loc_all   device complex128[N_r][N_t][N_t]: the local Green's function of every
+ *               site in site order (dyson_iterate with src = 0..N_r-1)
+ *   sig_out     device complex128[N_r][N_t][N_t]
+ *   ws          device workspace of scd_sigma2_workspace_bytes()
+ * Cost: O(N_r N_t^4) on the vector units.
+ */
+int sigma2_build(const scd_problem* p, const double* V, const double* U, const double* J,
+                 const void* S, const void* G_loc_all, void* sig_out, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/*
+ * Dressed block diagonal for eq. Glatt with the self-energy Sigma =
+ * calG^-1 o Sigma~ o calG^-1 (eq. defnSigma; contour products carry the
+ * quadrature weights): the contour inverse of calG_i^-1 - Sigma_i is
+ *   S'_i = S_i (S_i - Sigma~_i)^-1 S_i,
+ * so dyson_iterate with S' in place of S solves the lattice Dyson equation with
+ * Sigma.  Gauss-Jordan elimination with partial pivoting per site.
+ *   S, sig   device complex128[N_r][N_t][N_t];  S_out the same (not aliasing S)
+ * Errors: SCD_ENAN if S - Sigma~ is singular on a site.  Blocks until done.
+ */
+int sigma2_dress(const scd_problem* p, const void* S, const void* sig, void* S_out, void* ws,
+                 size_t ws_bytes, void* stream);
+
+/*
  * Device workspace (bytes) for dyson_adjoint at precision prec.
  */
 int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* bytes);

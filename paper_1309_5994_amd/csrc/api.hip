@@ -1009,6 +1009,87 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
 
 }  // namespace
 
+namespace {
+
+struct S2Layout {
+    size_t off_k, off_part, off_aug, off_flag, total;
+};
+
+S2Layout s2_layout(const Geom& g) {
+    S2Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t blocks = (size_t)g.n_r * g.n_t * g.n_t * sizeof(double2);
+    L.off_k = take(blocks);
+    L.off_part = take(blocks);
+    L.off_aug = take(2 * blocks);
+    L.off_flag = take(sizeof(int));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+int scd_sigma2_workspace_bytes(const scd_problem* p, size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
+    *bytes = s2_layout(g).total;
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int sigma2_build(const scd_problem* p, const double* V, const double* U, const double* J,
+                 const void* S, const void* G_loc_all, void* sig_out, void* ws, size_t ws_bytes,
+                 void* stream) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!V || !U || !J || !S || !G_loc_all || !sig_out || !ws)
+        return fail(SCD_EINVAL, "V, U, J, S, G_loc_all, sig_out and ws must be non-NULL");
+    const S2Layout L = s2_layout(g);
+    if (ws_bytes < L.total)
+        return fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    SCD_HIP(launch_sigma2(g, V, U, J, (const double2*)S, (const double2*)G_loc_all,
+                          (double2*)(base + L.off_k), (double2*)(base + L.off_part),
+                          (double2*)sig_out, st),
+            "sigma2 launch");
+    g_last_error.clear();
+    return SCD_OK;
+}
+
+int sigma2_dress(const scd_problem* p, const void* S, const void* sig, void* S_out, void* ws,
+                 size_t ws_bytes, void* stream) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!S || !sig || !S_out || !ws) return fail(SCD_EINVAL, "S, sig, S_out and ws must be non-NULL");
+    if (S_out == S) return fail(SCD_EINVAL, "S_out must not alias S");
+    const S2Layout L = s2_layout(g);
+    if (ws_bytes < L.total)
+        return fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    int* flag = (int*)(base + L.off_flag);
+    SCD_HIP(hipMemsetAsync(flag, 0, sizeof(int), st), "flag clear");
+    SCD_HIP(launch_dress(g, (const double2*)S, (const double2*)sig, (double2*)(base + L.off_aug),
+                         (double2*)S_out, flag, st),
+            "dress launch");
+    int h = 0;
+    SCD_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+    SCD_HIP(hipStreamSynchronize(st), "dress sync");
+    if (h) return fail(SCD_ENAN, "S - Sigma~ is singular on some site");
+    g_last_error.clear();
+    return SCD_OK;
+}
+
 int double_occupancy(const scd_problem* p, const void* G_loc, const void* G_nn, const double* J,
                      const double* V, const double* U, const int32_t* src, int32_t n_src,
                      double* d_out, double* frac_out, void* stream) {

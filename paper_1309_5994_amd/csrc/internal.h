@@ -142,6 +142,13 @@ hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipSt
 hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st);
+// ---- second-order self-energy (sigma2.hip) ----
+hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const double* J,
+                         const double2* S, const double2* G_loc_all, double2* K, double2* part,
+                         double2* sig, hipStream_t st);
+hipError_t launch_dress(const Geom& g, const double2* S, const double2* sig, double2* aug,
+                        double2* S_out, int* singular, hipStream_t st);
+
 // ---- point-group reduction (sym.hip) ----
 // The lattice's point group about its centre: C4v (8 elements) for Lx == Ly,
 // else C2v (4).  Element e applies mirror x (bit 0), mirror y (bit 1), then

@@ -1,0 +1,358 @@
+// Second-order strong-coupling self-energy (Sec. III of arXiv:1309.5994,
+// eq. defnSigmatilde, eq. defnSigma) and the dressed block diagonal it gives.
+//
+//   Sigma~_i(a, b) = - sum_{s1} sum_{c,d} G~_{up s1}(a, d; c, b) K_i(c, d),
+//   K_i(c, d)      = w_c J(z_c) [sum_{k in nbr(i)} G_loc,k(c, d)] J(z_d) w_d,
+//
+// with the cumulant G~ = G^II + G(a,c) G(d,b) delta_{up s1} - G(a,b) G(d,c)
+// (G = S_i, the atomic Green's function).  The one-particle terms of the
+// cumulant collapse to matrix algebra,
+//
+//   Sigma~ = - sum_{c,d} K(c,d) [G^II_{up up} + G^II_{up dn}](a, d; c, b)
+//            + 2 S(a, b) tr(K S^T ... ) - (S K S)(a, b),
+//
+// precisely  + 2 S(a,b) sum_{c,d} K(c,d) S(d,c)  - sum_{c,d} S(a,c) K(c,d) S(d,b),
+// so only the two-particle part needs the N_t^4 sum.  G^II is evaluated on the
+// fly in the number basis |0>, |dn>, |up>, |up dn> (eq. cumulanttabulation):
+// the four operators c_up(a) c_s1(d) c^dag_s1(c) c^dag_up(b) are put in contour
+// order (later first; at one contour index creation operators count as later,
+// operators of one kind keep their written order) with the permutation's sign,
+// and every initial state is carried through the ordered product, each
+// operator contributing exp(i Theta_after(z) - i Theta_before(z)); the phases
+// and the Boltzmann weight are combined in one exponent, so imaginary-branch
+// factors never overflow.
+//
+// The dressed block (the contour inverse of calG^-1 - Sigma, with
+// Sigma = calG^-1 o Sigma~ o calG^-1) is S' = S (S - Sigma~)^-1 S in plain
+// matrices; the lattice solve with S' in place of S is eq. Glatt with Sigma.
+#include "internal.h"
+
+namespace scd {
+namespace {
+
+constexpr int kS2Threads = 256;
+
+__device__ inline double2 cmul2(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Transitions of the four operators c_up, c_dn, c^dag_up, c^dag_dn on the
+// states 0 |0>, 1 |dn>, 2 |up>, 3 |up dn> = c^dag_up c^dag_dn |0>:
+// next state (-1: annihilated) and sign.
+__constant__ int kNext[4][4] = {{-1, -1, 0, 1}, {-1, 0, -1, 2}, {2, 3, -1, -1}, {1, -1, 3, -1}};
+__constant__ double kAmp[4][4] = {{0, 0, 1, 1}, {0, 1, 0, -1}, {1, 1, 0, 0}, {1, 0, -1, 0}};
+
+// K_i = diag(wJ) (sum of the neighbours' G_loc) diag(wJ), one thread per element.
+__global__ __launch_bounds__(256)
+void k_build_kernel(const double2* __restrict__ G_loc, const double* __restrict__ J,
+                    double2* __restrict__ K, Geom g) {
+    const int n_t = g.n_t;
+    const size_t per = (size_t)n_t * n_t;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < (size_t)g.n_r * per;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / per);
+        const int cd = (int)(e - (size_t)i * per);
+        const int c = cd / n_t, d = cd - (cd / n_t) * n_t;
+        int nb[4];
+        site_neighbours(i, g.Lx, g.Ly, g.periodic, nb);
+        double2 s = make_double2(0.0, 0.0);
+        for (int q = 0; q < 4; ++q)
+            if (nb[q] >= 0) {
+                const double2 v = G_loc[(size_t)nb[q] * per + cd];
+                s.x += v.x;
+                s.y += v.y;
+            }
+        const double2 wc = contour_wj(c, g.n_real, g.dt, g.dtau, J);
+        const double2 wd = contour_wj(d, g.n_real, g.dt, g.dtau, J);
+        K[e] = cmul2(cmul2(wc, s), wd);
+    }
+}
+
+// Contour phases of the site (LDS): Theta_1 = eps (z - t_min) (states |dn>,
+// |up>) and Theta_3 = 2 eps (z - t_min) + int U dz (state |up dn>).
+__device__ void site_phases(const double* U, double eps, Geom g, double* t1r, double* t1i,
+                            double* t3r, double* t3i, double* cum) {
+    const int n_t = g.n_t, n_real = g.n_real;
+    if (threadIdx.x == 0) {
+        double acc = 0.0;
+        cum[0] = 0.0;
+        for (int k = 1; k < n_real; ++k) {
+            acc += 0.5 * (U[k] + U[k - 1]) * g.dt;
+            cum[k] = acc;
+        }
+    }
+    __syncthreads();
+    for (int a = threadIdx.x; a < n_t; a += blockDim.x) {
+        double zr, zi, pr, pi;
+        if (a < 2 * n_real) {
+            const int k = a < n_real ? a : 2 * n_real - 1 - a;
+            zr = k * g.dt;
+            zi = 0.0;
+            pr = cum[k];
+            pi = 0.0;
+        } else {
+            const double tau = (a - 2 * n_real + 1) * g.dtau;
+            zr = 0.0;
+            zi = -tau;
+            pr = 0.0;
+            pi = -tau * U[0];
+        }
+        t1r[a] = eps * zr;
+        t1i[a] = eps * zi;
+        t3r[a] = 2.0 * eps * zr + pr;
+        t3i[a] = 2.0 * eps * zi + pi;
+    }
+    __syncthreads();
+}
+
+// part(a, b) = - sum_{c,d} K(c,d) [G^II_{up up} + G^II_{up dn}](a, d; c, b):
+// one thread per (a, b), one workgroup per (site, 256 outputs).
+__global__ __launch_bounds__(kS2Threads)
+void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict__ V,
+                        const double* __restrict__ U, double2* __restrict__ out, Geom g) {
+    __shared__ double t1r[kMaxNt], t1i[kMaxNt], t3r[kMaxNt], t3i[kMaxNt];
+    __shared__ double cum[kMaxNt];
+    const int site = blockIdx.y;
+    const int n_t = g.n_t;
+    const double U0 = U[0];
+    const double eps = V[site] - 0.5 * U0 - g.mu;
+    site_phases(U, eps, g, t1r, t1i, t3r, t3i, cum);
+    // log Boltzmann weights of the four states at t_min
+    const double lw1 = -g.beta * eps, lw3 = -g.beta * (2.0 * eps + U0);
+    const double mx = fmax(fmax(0.0, lw1), lw3);
+    const double lz = mx + log(exp(-mx) + 2.0 * exp(lw1 - mx) + exp(lw3 - mx));
+    const double lp[4] = {-lz, lw1 - lz, lw1 - lz, lw3 - lz};
+
+    const int e = blockIdx.x * kS2Threads + threadIdx.x;
+    if (e >= n_t * n_t) return;
+    const int a = e / n_t, b = e - (e / n_t) * n_t;
+    const double2* Ki = K + (size_t)site * n_t * n_t;
+    auto th_re = [&](int st, int z) { return st == 0 ? 0.0 : (st == 3 ? t3r[z] : t1r[z]); };
+    auto th_im = [&](int st, int z) { return st == 0 ? 0.0 : (st == 3 ? t3i[z] : t1i[z]); };
+    double acc_r = 0.0, acc_i = 0.0;
+    for (int c = 0; c < n_t; ++c) {
+        for (int d = 0; d < n_t; ++d) {
+            const double2 k = Ki[(size_t)c * n_t + d];
+            double gr = 0.0, gi = 0.0;
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1) {
+                // written order: c_up(a), c_s1(d), c^dag_s1(c), c^dag_up(b)
+                int kind[4] = {0, s1 == 0 ? 0 : 1, s1 == 0 ? 2 : 3, 2};
+                int pt[4] = {a, d, c, b};
+                int key[4] = {2 * a, 2 * d, 2 * c + 1, 2 * b + 1};
+                // stable insertion sort, descending key, tracking the parity
+                double sgn = 1.0;
+#pragma unroll
+                for (int i = 1; i < 4; ++i) {
+#pragma unroll
+                    for (int j = i; j > 0; --j) {
+                        if (key[j] > key[j - 1]) {
+                            int t = key[j]; key[j] = key[j - 1]; key[j - 1] = t;
+                            t = kind[j]; kind[j] = kind[j - 1]; kind[j - 1] = t;
+                            t = pt[j]; pt[j] = pt[j - 1]; pt[j - 1] = t;
+                            sgn = -sgn;
+                        }
+                    }
+                }
+                // trace over initial states: apply the ordered product right to left
+#pragma unroll
+                for (int nu = 0; nu < 4; ++nu) {
+                    int st = nu;
+                    double amp = sgn;
+                    double xr = lp[nu], xi = 0.0;     // exponent of the path
+#pragma unroll
+                    for (int q = 3; q >= 0 && st >= 0; --q) {
+                        const int nx = kNext[kind[q]][st];
+                        if (nx < 0) {
+                            st = -1;
+                            break;
+                        }
+                        amp *= kAmp[kind[q]][st];
+                        // exp(i (Theta_nx - Theta_st)(z)) = exp(-dIm + i dRe)
+                        const int z = pt[q];
+                        xr -= th_im(nx, z) - th_im(st, z);
+                        xi += th_re(nx, z) - th_re(st, z);
+                        st = nx;
+                    }
+                    if (st != nu) continue;
+                    double s, co;
+                    sincos(xi, &s, &co);
+                    const double m = amp * exp(xr);
+                    gr += m * co;
+                    gi += m * s;
+                }
+            }
+            // G^II carries (-i)^2 = -1; part = - K G^II = + K (gr + i gi)
+            acc_r += k.x * gr - k.y * gi;
+            acc_i += k.x * gi + k.y * gr;
+        }
+    }
+    out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);
+}
+
+// Sigma~ = part + 2 S(a,b) tr(K S^T-order) - (S K S)(a,b): one workgroup per
+// (site, 256 outputs); T_i = sum_{c,d} K(c,d) S(d,c) reduced per workgroup.
+__global__ __launch_bounds__(kS2Threads)
+void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restrict__ K,
+                           const double2* __restrict__ part, double2* __restrict__ sig,
+                           Geom g) {
+    __shared__ double red_r[kS2Threads], red_i[kS2Threads];
+    const int site = blockIdx.y;
+    const int n_t = g.n_t;
+    const size_t per = (size_t)n_t * n_t;
+    const double2* Si = S + (size_t)site * per;
+    const double2* Ki = K + (size_t)site * per;
+    double tr = 0.0, ti = 0.0;
+    for (int cd = threadIdx.x; cd < n_t * n_t; cd += kS2Threads) {
+        const int c = cd / n_t, d = cd - (cd / n_t) * n_t;
+        const double2 v = cmul2(Ki[cd], Si[(size_t)d * n_t + c]);
+        tr += v.x;
+        ti += v.y;
+    }
+    red_r[threadIdx.x] = tr;
+    red_i[threadIdx.x] = ti;
+    __syncthreads();
+    for (int s = kS2Threads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red_r[threadIdx.x] += red_r[threadIdx.x + s];
+            red_i[threadIdx.x] += red_i[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const double2 T = make_double2(red_r[0], red_i[0]);
+    const int e = blockIdx.x * kS2Threads + threadIdx.x;
+    if (e >= n_t * n_t) return;
+    const int a = e / n_t, b = e - (e / n_t) * n_t;
+    // (S K S)(a, b) = sum_c S(a,c) sum_d K(c,d) S(d,b)
+    double2 sks = make_double2(0.0, 0.0);
+    for (int c = 0; c < n_t; ++c) {
+        double2 inner = make_double2(0.0, 0.0);
+        for (int d = 0; d < n_t; ++d) {
+            const double2 v = cmul2(Ki[(size_t)c * n_t + d], Si[(size_t)d * n_t + b]);
+            inner.x += v.x;
+            inner.y += v.y;
+        }
+        const double2 v = cmul2(Si[(size_t)a * n_t + c], inner);
+        sks.x += v.x;
+        sks.y += v.y;
+    }
+    const double2 st = cmul2(Si[e], T);
+    const double2 p = part[(size_t)site * per + e];
+    sig[(size_t)site * per + e] = make_double2(p.x + 2.0 * st.x - sks.x, p.y + 2.0 * st.y - sks.y);
+}
+
+// S' = S (S - Sigma~)^-1 S per site: Gauss-Jordan elimination with partial
+// pivoting of [S - Sigma~ | S] (one workgroup per site, the augmented matrix
+// in the workspace), then the product with S.
+__global__ __launch_bounds__(kS2Threads)
+void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig,
+                  double2* __restrict__ aug, double2* __restrict__ S_out, Geom g,
+                  int* __restrict__ singular) {
+    __shared__ double rmax[kS2Threads];
+    __shared__ int ridx[kS2Threads];
+    __shared__ int piv_s;
+    const int site = blockIdx.x;
+    const int n = g.n_t, w = 2 * n;
+    const size_t per = (size_t)n * n;
+    const double2* Si = S + (size_t)site * per;
+    const double2* Gi = sig + (size_t)site * per;
+    double2* A = aug + (size_t)site * n * w;                 // [n][2n]
+    for (int e = threadIdx.x; e < n * w; e += kS2Threads) {
+        const int r = e / w, c = e - (e / w) * w;
+        if (c < n) {
+            const double2 s = Si[(size_t)r * n + c], x = Gi[(size_t)r * n + c];
+            A[e] = make_double2(s.x - x.x, s.y - x.y);
+        } else {
+            A[e] = Si[(size_t)r * n + (c - n)];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // pivot: largest |A(r, k)| for r >= k
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + threadIdx.x; r < n; r += kS2Threads) {
+            const double2 v = A[(size_t)r * w + k];
+            const double m = fabs(v.x) + fabs(v.y);
+            if (m > best) {
+                best = m;
+                bi = r;
+            }
+        }
+        rmax[threadIdx.x] = best;
+        ridx[threadIdx.x] = bi;
+        __syncthreads();
+        for (int s = kS2Threads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s && rmax[threadIdx.x + s] > rmax[threadIdx.x]) {
+                rmax[threadIdx.x] = rmax[threadIdx.x + s];
+                ridx[threadIdx.x] = ridx[threadIdx.x + s];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            piv_s = ridx[0];
+            if (!(rmax[0] > 0.0)) singular[0] = 1;
+        }
+        __syncthreads();
+        const int p = piv_s;
+        if (p != k)
+            for (int c = threadIdx.x; c < w; c += kS2Threads) {
+                const double2 t = A[(size_t)k * w + c];
+                A[(size_t)k * w + c] = A[(size_t)p * w + c];
+                A[(size_t)p * w + c] = t;
+            }
+        __syncthreads();
+        // scale the pivot row by 1 / A(k, k)
+        const double2 pv = A[(size_t)k * w + k];
+        const double den = pv.x * pv.x + pv.y * pv.y;
+        const double2 inv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0, 0);
+        __syncthreads();
+        for (int c = threadIdx.x; c < w; c += kS2Threads)
+            A[(size_t)k * w + c] = cmul2(A[(size_t)k * w + c], inv);
+        __syncthreads();
+        // eliminate column k from every other row
+        for (int e = threadIdx.x; e < n * w; e += kS2Threads) {
+            const int r = e / w, c = e - (e / w) * w;
+            if (r == k || c == k) continue;
+            const double2 f = A[(size_t)r * w + k];
+            const double2 v = cmul2(f, A[(size_t)k * w + c]);
+            A[e] = make_double2(A[e].x - v.x, A[e].y - v.y);
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < n; r += kS2Threads)
+            if (r != k) A[(size_t)r * w + k] = make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+    // S' = S Y, Y = right half of A
+    for (int e = threadIdx.x; e < n * n; e += kS2Threads) {
+        const int r = e / n, c = e - (e / n) * n;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int q = 0; q < n; ++q) {
+            const double2 v = cmul2(Si[(size_t)r * n + q], A[(size_t)q * w + n + c]);
+            acc.x += v.x;
+            acc.y += v.y;
+        }
+        S_out[(size_t)site * per + e] = acc;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const double* J,
+                         const double2* S, const double2* G_loc_all, double2* K, double2* part,
+                         double2* sig, hipStream_t st) {
+    hipLaunchKernelGGL(k_build_kernel, dim3(2048), dim3(256), 0, st, G_loc_all, J, K, g);
+    const dim3 grid((g.n_t * g.n_t + kS2Threads - 1) / kS2Threads, g.n_r);
+    hipLaunchKernelGGL(sigma2_pair_kernel, grid, dim3(kS2Threads), 0, st, K, V, U, part, g);
+    hipLaunchKernelGGL(sigma2_onebody_kernel, grid, dim3(kS2Threads), 0, st, S, K, part, sig, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_dress(const Geom& g, const double2* S, const double2* sig, double2* aug,
+                        double2* S_out, int* singular, hipStream_t st) {
+    hipLaunchKernelGGL(dress_kernel, dim3(g.n_r), dim3(kS2Threads), 0, st, S, sig, aug, S_out, g,
+                       singular);
+    return hipGetLastError();
+}
+
+}  // namespace scd

@@ -98,6 +98,13 @@ def lib():
     L.dyson_gmres.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                               _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.scd_sigma2_workspace_bytes.restype = ctypes.c_int
+    L.scd_sigma2_workspace_bytes.argtypes = [_P(Problem), _P(ctypes.c_size_t)]
+    L.sigma2_build.restype = ctypes.c_int
+    L.sigma2_build.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                               _vp]
+    L.sigma2_dress.restype = ctypes.c_int
+    L.sigma2_dress.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     L.double_occupancy.restype = ctypes.c_int
     L.double_occupancy.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                    _vp, _vp, _vp]
@@ -319,6 +326,46 @@ def local_observables(prob: Problem, G_loc, G_nn, J, want_ekin=True, stream=None
     _check(lib().local_observables(ctypes.byref(prob), _ptr(G_loc), _ptr(G_nn if want_ekin else None),
                                    _ptr(J), n_src, _ptr(n), _ptr(ekin), _stream(stream)))
     return n, ekin
+
+
+def sigma2_workspace_bytes(prob: Problem) -> int:
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_sigma2_workspace_bytes(ctypes.byref(prob), ctypes.byref(out)))
+    return out.value
+
+
+def sigma2_build(prob: Problem, V, U, J, S, G_loc_all, out=None, ws=None, stream=None):
+    """Sigma~ [N_r, N_t, N_t] (eq. defnSigmatilde) from every site's local G."""
+    import torch
+    shape = (prob.n_r, prob.n_t, prob.n_t)
+    _need(S, torch.complex128, shape, "S")
+    _need(G_loc_all, torch.complex128, shape, "G_loc_all")
+    _need(V, torch.float64, (prob.n_r,), "V")
+    _need(U, torch.float64, (prob.n_real,), "U")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    out = torch.empty(shape, dtype=torch.complex128, device=S.device) if out is None else out
+    need = sigma2_workspace_bytes(prob)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=S.device)
+    _check(lib().sigma2_build(ctypes.byref(prob), _ptr(V), _ptr(U), _ptr(J), _ptr(S),
+                              _ptr(G_loc_all), _ptr(out), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                              _stream(stream)))
+    return out
+
+
+def sigma2_dress(prob: Problem, S, sig, out=None, ws=None, stream=None):
+    """S' = S (S - Sigma~)^-1 S per site (eq. defnSigma, eq. Glatt)."""
+    import torch
+    shape = (prob.n_r, prob.n_t, prob.n_t)
+    _need(S, torch.complex128, shape, "S")
+    _need(sig, torch.complex128, shape, "sig")
+    out = torch.empty(shape, dtype=torch.complex128, device=S.device) if out is None else out
+    need = sigma2_workspace_bytes(prob)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=S.device)
+    _check(lib().sigma2_dress(ctypes.byref(prob), _ptr(S), _ptr(sig), _ptr(out), _ptr(ws),
+                              ctypes.c_size_t(ws.numel()), _stream(stream)))
+    return out
 
 
 def double_occupancy(prob: Problem, G_loc, G_nn, J, V, U, src, want_fraction=True,

@@ -315,6 +315,40 @@ int sigma2_dress(const scd_problem* p, const void* S, const void* sig, void* S_o
                  size_t ws_bytes, void* stream);
 
 /*
+ * Device workspace (bytes) of dyson_selfconsistent.
+ */
+int scd_selfconsistent_workspace_bytes(const scd_problem* p, int32_t block_sites, int32_t prec,
+                                       size_t* bytes);
+
+/*
+ * The self-consistent second-order strong-coupling solution (Sec. III):
+ * S = sigma_build(V, U); Sigma~ = 0; repeat
+ *     G_loc of every site = dyson_iterate with the dressed blocks sigma2_dress(S, Sigma~),
+ *     Sigma~_new = sigma2_build(G_loc),
+ *     d = |Sigma~_new - Sigma~|_F / N_bd + max |Sigma~_new - Sigma~|,  N_bd = N_r N_t^2,
+ *     Sigma~ = lam Sigma~_new + (1 - lam) Sigma~                   (eq. Sigmamix)
+ * until d <= delta_sc, then one last solve with the final Sigma~ (the norm is
+ * taken on Sigma~, of which Sigma = calG^-1 o Sigma~ o calG^-1 is a fixed
+ * linear image; the paper uses lam ~ 0.7 and delta_sc ~ 1e-8 U).
+ *   V, U, J      device inputs as sigma_build / dyson_iterate
+ *   lam          mixing parameter in (0, 1];  delta_sc > 0;  max_sc >= 1 steps
+ *   block_sites, prec, tol, max_iter   passed to every dyson_iterate (all N_r sources)
+ *   S_out        device complex128[N_r][N_t][N_t]: the atomic S
+ *   sig_out      device complex128[N_r][N_t][N_t]: the final Sigma~
+ *   G_loc, G_nn  device complex128[N_r][N_t][N_t], [N_r][4][N_t][N_t] (G_nn may be NULL)
+ *                of the last solve, in site order
+ *   sc_iter, sc_norm  host (nullable): steps taken and the last d
+ *   st           host (nullable): the lattice solves' statistics summed
+ * Errors as dyson_iterate and sigma2_dress; SCD_ENOTCONV if d > delta_sc after
+ * max_sc steps (outputs hold the last state).  Blocks until done.
+ */
+int dyson_selfconsistent(const scd_problem* p, const double* V, const double* U, const double* J,
+                         double lam, double delta_sc, int32_t max_sc, int32_t block_sites,
+                         int32_t prec, double tol, int32_t max_iter, void* S_out, void* sig_out,
+                         void* G_loc, void* G_nn, void* ws, size_t ws_bytes, int32_t* sc_iter,
+                         double* sc_norm, scd_stats* st, void* stream);
+
+/*
  * Device workspace (bytes) for dyson_adjoint at precision prec.
  */
 int scd_adjoint_workspace_bytes(const scd_problem* p, int32_t prec, size_t* bytes);

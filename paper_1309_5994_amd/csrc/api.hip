@@ -1090,6 +1090,138 @@ int sigma2_dress(const scd_problem* p, const void* S, const void* sig, void* S_o
     return SCD_OK;
 }
 
+int dyson_selfconsistent(const scd_problem* p, const double* V, const double* U, const double* J,
+                         double lam, double delta_sc, int32_t max_sc, int32_t block_sites,
+                         int32_t prec, double tol, int32_t max_iter, void* S_out, void* sig_out,
+                         void* G_loc, void* G_nn, void* ws, size_t ws_bytes, int32_t* sc_iter,
+                         double* sc_norm, scd_stats* st_out, void* stream) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!V || !U || !J || !S_out || !sig_out || !G_loc || !ws)
+        return fail(SCD_EINVAL, "V, U, J, S_out, sig_out, G_loc and ws must be non-NULL");
+    if (!(lam > 0.0 && lam <= 1.0)) return fail(SCD_EINVAL, "lam must be in (0, 1]");
+    if (!(delta_sc > 0.0)) return fail(SCD_EINVAL, "delta_sc must be > 0");
+    if (max_sc < 1) return fail(SCD_EINVAL, "max_sc must be >= 1");
+    size_t need = 0;
+    size_t dyson_bytes = 0, s2_bytes = 0;
+    rc = scd_workspace_bytes(p, g.n_r, block_sites, prec, &dyson_bytes);
+    if (rc) return rc;
+    rc = scd_sigma2_workspace_bytes(p, &s2_bytes);
+    if (rc) return rc;
+    const size_t blocks = align256((size_t)g.n_r * g.n_t * g.n_t * sizeof(double2));
+    constexpr int kParts = 1024;
+    const size_t off_dressed = 0, off_new = blocks, off_s2 = 2 * blocks,
+                 off_dyson = off_s2 + align256(s2_bytes),
+                 off_part = off_dyson + align256(dyson_bytes);
+    need = off_part + align256(2 * kParts * sizeof(double));
+    if (ws_bytes < need) return fail(SCD_ENOMEM, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    char* base = (char*)ws;
+    double2* S = (double2*)S_out;
+    double2* sig = (double2*)sig_out;
+    double2* dressed = (double2*)(base + off_dressed);
+    double2* fresh = (double2*)(base + off_new);
+    void* ws2 = base + off_s2;
+    void* wsd = base + off_dyson;
+    double* part = (double*)(base + off_part);
+    const size_t n_el = (size_t)g.n_r * g.n_t * g.n_t;
+    std::vector<int32_t> every(g.n_r);
+    for (int i = 0; i < g.n_r; ++i) every[i] = i;
+    scd_stats total;
+    std::memset(&total, 0, sizeof total);
+    auto accumulate = [&](const scd_stats& s) {
+        total.n_blocks += s.n_blocks;
+        total.sweeps_total += s.sweeps_total;
+        total.sweeps_max = std::max(total.sweeps_max, s.sweeps_max);
+        total.fp64_sweeps += s.fp64_sweeps;
+        total.lowp_sweeps += s.lowp_sweeps;
+        total.final_err = s.final_err;
+        total.rho_est = s.rho_est;
+        total.gemm_flops += s.gemm_flops;
+        total.seconds += s.seconds;
+        total.sweep_kernel_seconds += s.sweep_kernel_seconds;
+        total.lowp_kernel_seconds += s.lowp_kernel_seconds;
+        total.sweep_launches += s.sweep_launches;
+        total.lowp_launches += s.lowp_launches;
+    };
+    rc = sigma_build(p, V, U, S, stream);
+    if (rc) return rc;
+    SCD_HIP(hipMemsetAsync(sig, 0, n_el * sizeof(double2), st), "clear Sigma~");
+    int it = 0;
+    double norm = 0.0;
+    int code = SCD_ENOTCONV;
+    for (it = 1; it <= max_sc; ++it) {
+        // G_loc of every site with the current dressed blocks
+        rc = sigma2_dress(p, S, sig, dressed, ws2, s2_bytes, stream);
+        if (rc) return rc;
+        scd_stats s1;
+        rc = dyson_iterate(p, dressed, J, every.data(), g.n_r, block_sites, prec, tol, max_iter,
+                           nullptr, G_loc, G_nn, wsd, dyson_bytes, &s1, stream);
+        accumulate(s1);
+        if (rc) return rc;
+        rc = sigma2_build(p, V, U, J, S, G_loc, fresh, ws2, s2_bytes, stream);
+        if (rc) return rc;
+        SCD_HIP(launch_mix(fresh, sig, lam, n_el, part, kParts, st), "mix launch");
+        std::vector<double> h(2 * kParts);
+        SCD_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, st),
+                "copy partials");
+        SCD_HIP(hipStreamSynchronize(st), "mix sync");
+        double s2 = 0.0, mx = 0.0;
+        for (int w = 0; w < kParts; ++w) {
+            s2 += h[2 * w];
+            mx = (h[2 * w + 1] > mx || h[2 * w + 1] != h[2 * w + 1]) ? h[2 * w + 1] : mx;
+        }
+        // |Delta|_F / N_bd + |Delta|_max (Sec. III), on Sigma~
+        norm = std::sqrt(s2) / (double)n_el + mx;
+        if (!std::isfinite(norm)) {
+            code = fail(SCD_ENAN, "NaN or Inf in Sigma~ at self-consistency step %d", it);
+            break;
+        }
+        if (norm <= delta_sc) {
+            code = SCD_OK;
+            break;
+        }
+    }
+    if (code != SCD_ENAN) {
+        // the solve with the final (mixed) self-energy
+        rc = sigma2_dress(p, S, sig, dressed, ws2, s2_bytes, stream);
+        if (rc) return rc;
+        scd_stats s1;
+        rc = dyson_iterate(p, dressed, J, every.data(), g.n_r, block_sites, prec, tol, max_iter,
+                           nullptr, G_loc, G_nn, wsd, dyson_bytes, &s1, stream);
+        accumulate(s1);
+        if (rc) return rc;
+    }
+    if (sc_iter) *sc_iter = it > max_sc ? max_sc : it;
+    if (sc_norm) *sc_norm = norm;
+    total.status = code;
+    if (st_out) *st_out = total;
+    if (code == SCD_ENOTCONV)
+        return fail(SCD_ENOTCONV, "self-consistency not reached after %d steps (norm %g)", max_sc,
+                    norm);
+    if (code == SCD_OK) g_last_error.clear();
+    return code;
+}
+
+int scd_selfconsistent_workspace_bytes(const scd_problem* p, int32_t block_sites, int32_t prec,
+                                       size_t* bytes) {
+    Geom g;
+    int rc = check_problem(p, kMaxNt, &g);
+    if (rc) return rc;
+    if (!bytes) return fail(SCD_EINVAL, "bytes is NULL");
+    size_t dyson_bytes = 0, s2_bytes = 0;
+    rc = scd_workspace_bytes(p, g.n_r, block_sites, prec, &dyson_bytes);
+    if (rc) return rc;
+    rc = scd_sigma2_workspace_bytes(p, &s2_bytes);
+    if (rc) return rc;
+    const size_t blocks = align256((size_t)g.n_r * g.n_t * g.n_t * sizeof(double2));
+    *bytes = 2 * blocks + align256(s2_bytes) + align256(dyson_bytes) +
+             align256(2 * 1024 * sizeof(double));
+    g_last_error.clear();
+    return SCD_OK;
+}
+
 int double_occupancy(const scd_problem* p, const void* G_loc, const void* G_nn, const double* J,
                      const double* V, const double* U, const int32_t* src, int32_t n_src,
                      double* d_out, double* frac_out, void* stream) {

@@ -148,6 +148,10 @@ hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const 
                          double2* sig, hipStream_t st);
 hipError_t launch_dress(const Geom& g, const double2* S, const double2* sig, double2* aug,
                         double2* S_out, int* singular, hipStream_t st);
+// sig <- lam fresh + (1 - lam) sig; part[2 w] = sum |fresh - sig|^2, part[2 w + 1] =
+// max |fresh - sig| over the elements of workgroup w (n_part workgroups).
+hipError_t launch_mix(const double2* fresh, double2* sig, double lam, size_t n, double* part,
+                      int n_part, hipStream_t st);
 
 // ---- point-group reduction (sym.hip) ----
 // The lattice's point group about its centre: C4v (8 elements) for Lx == Ly,

@@ -9,9 +9,8 @@
 // cumulant collapse to matrix algebra,
 //
 //   Sigma~ = - sum_{c,d} K(c,d) [G^II_{up up} + G^II_{up dn}](a, d; c, b)
-//            + 2 S(a, b) tr(K S^T ... ) - (S K S)(a, b),
+//            + 2 S(a,b) sum_{c,d} K(c,d) S(d,c) - sum_{c,d} S(a,c) K(c,d) S(d,b),
 //
-// precisely  + 2 S(a,b) sum_{c,d} K(c,d) S(d,c)  - sum_{c,d} S(a,c) K(c,d) S(d,b),
 // so only the two-particle part needs the N_t^4 sum.  G^II is evaluated on the
 // fly in the number basis |0>, |dn>, |up>, |up dn> (eq. cumulanttabulation):
 // the four operators c_up(a) c_s1(d) c^dag_s1(c) c^dag_up(b) are put in contour
@@ -190,8 +189,8 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);
 }
 
-// Sigma~ = part + 2 S(a,b) tr(K S^T-order) - (S K S)(a,b): one workgroup per
-// (site, 256 outputs); T_i = sum_{c,d} K(c,d) S(d,c) reduced per workgroup.
+// Sigma~ = part + 2 S(a,b) T - (S K S)(a,b), T = sum_{c,d} K(c,d) S(d,c): one
+// workgroup per (site, 256 outputs), T reduced inside each workgroup.
 __global__ __launch_bounds__(kS2Threads)
 void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restrict__ K,
                            const double2* __restrict__ part, double2* __restrict__ sig,
@@ -336,7 +335,47 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
     }
 }
 
+// Linear mixing of eq. Sigmamix, sig <- lam new + (1 - lam) sig, with the
+// per-workgroup partial sum of |new - sig|^2 and maximum of |new - sig|.
+__global__ __launch_bounds__(256)
+void mix_kernel(const double2* __restrict__ fresh, double2* __restrict__ sig, double lam,
+                size_t n, double* __restrict__ part) {
+    __shared__ double rs[256], rm[256];
+    double s2 = 0.0, mx = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const double2 a = fresh[e], b = sig[e];
+        const double dr = a.x - b.x, di = a.y - b.y;
+        const double m2 = dr * dr + di * di;
+        s2 += m2;
+        mx = fmax(mx, sqrt(m2));
+        if (!(m2 == m2)) mx = m2;                     // keep a NaN
+        sig[e] = make_double2(lam * a.x + (1.0 - lam) * b.x, lam * a.y + (1.0 - lam) * b.y);
+    }
+    rs[threadIdx.x] = s2;
+    rm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            rs[threadIdx.x] += rs[threadIdx.x + s];
+            const double o = rm[threadIdx.x + s];
+            if (o > rm[threadIdx.x] || !(o == o)) rm[threadIdx.x] = o;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = rs[0];
+        part[2 * blockIdx.x + 1] = rm[0];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mix(const double2* fresh, double2* sig, double lam, size_t n, double* part,
+                      int n_part, hipStream_t st) {
+    hipLaunchKernelGGL(mix_kernel, dim3(n_part), dim3(256), 0, st, fresh, sig, lam, n, part);
+    return hipGetLastError();
+}
 
 hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const double* J,
                          const double2* S, const double2* G_loc_all, double2* K, double2* part,

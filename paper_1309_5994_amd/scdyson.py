@@ -105,6 +105,15 @@ def lib():
                                _vp]
     L.sigma2_dress.restype = ctypes.c_int
     L.sigma2_dress.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    L.scd_selfconsistent_workspace_bytes.restype = ctypes.c_int
+    L.scd_selfconsistent_workspace_bytes.argtypes = [_P(Problem), ctypes.c_int32, ctypes.c_int32,
+                                                     _P(ctypes.c_size_t)]
+    L.dyson_selfconsistent.restype = ctypes.c_int
+    L.dyson_selfconsistent.argtypes = [_P(Problem), _vp, _vp, _vp, ctypes.c_double,
+                                       ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp, _vp,
+                                       _vp, _vp, _vp, ctypes.c_size_t, _P(ctypes.c_int32),
+                                       _P(ctypes.c_double), _P(Stats), _vp]
     L.double_occupancy.restype = ctypes.c_int
     L.double_occupancy.argtypes = [_P(Problem), _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32,
                                    _vp, _vp, _vp]
@@ -366,6 +375,41 @@ def sigma2_dress(prob: Problem, S, sig, out=None, ws=None, stream=None):
     _check(lib().sigma2_dress(ctypes.byref(prob), _ptr(S), _ptr(sig), _ptr(out), _ptr(ws),
                               ctypes.c_size_t(ws.numel()), _stream(stream)))
     return out
+
+
+def dyson_selfconsistent(prob: Problem, V, U, J, lam=0.7, delta_sc=1e-8, max_sc=50,
+                         block_sites=None, prec=PREC_FP64, tol=1e-12, max_iter=500, ws=None,
+                         stream=None):
+    """The self-consistent second-order solution of Sec. III.  Returns dict(S,
+    sigma, G_loc, G_nn, iterations, norm, stats)."""
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    _need(V, torch.float64, (n_r,), "V")
+    _need(U, torch.float64, (prob.n_real,), "U")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    block_sites = n_r if block_sites is None else int(block_sites)
+    dev = V.device
+    S = torch.empty((n_r, n_t, n_t), dtype=torch.complex128, device=dev)
+    sig = torch.empty_like(S)
+    G_loc = torch.empty_like(S)
+    G_nn = torch.empty((n_r, 4, n_t, n_t), dtype=torch.complex128, device=dev)
+    out = ctypes.c_size_t(0)
+    _check(lib().scd_selfconsistent_workspace_bytes(ctypes.byref(prob), block_sites, int(prec),
+                                                    ctypes.byref(out)))
+    if ws is None or ws.numel() < out.value:
+        ws = torch.empty(out.value, dtype=torch.uint8, device=dev)
+    it = ctypes.c_int32(0)
+    norm = ctypes.c_double(0.0)
+    st = Stats()
+    rc = lib().dyson_selfconsistent(ctypes.byref(prob), _ptr(V), _ptr(U), _ptr(J), float(lam),
+                                    float(delta_sc), int(max_sc), block_sites, int(prec),
+                                    float(tol), int(max_iter), _ptr(S), _ptr(sig), _ptr(G_loc),
+                                    _ptr(G_nn), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                    ctypes.byref(it), ctypes.byref(norm), ctypes.byref(st),
+                                    _stream(stream))
+    _check(rc, st.as_dict())
+    return {"S": S, "sigma": sig, "G_loc": G_loc, "G_nn": G_nn, "iterations": it.value,
+            "norm": norm.value, "stats": st.as_dict()}
 
 
 def double_occupancy(prob: Problem, G_loc, G_nn, J, V, U, src, want_fraction=True,

@@ -61,3 +61,28 @@ def test_sigma2_dress_matches_oracle(device):
     # Sigma~ = 0 leaves S unchanged
     same = _np(B.sigma2_dress(prob, S, torch.zeros_like(S)))
     assert np.abs(same - _np(S)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("wl", [
+    W.custom(2, 2, 5, 4, J0=0.1, seed=3),
+    W.custom(3, 2, 7, 5, J0=0.1, seed=6),
+], ids=["2x2_nt14", "3x2_nt19"])
+def test_selfconsistent_loop_matches_oracle(wl, device):
+    """The whole loop of Sec. III (lam = 0.7, delta_sc = 1e-12) against the
+    oracle's loop with the dense lattice solve: the same number of steps, the
+    same Sigma~ and G_loc, the same densities."""
+    from paper_1309_5994_amd import scdyson as B
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.t_min)
+    sig_ref, G_ref, hist = SE.selfconsistent(wl.V, wl.U, wl.mu, wl.J, c, wl.Lx, wl.Ly,
+                                             wl.periodic, lam=0.7, delta_sc=1e-12, max_iter=60)
+    prob, V, U, J = gpu_inputs(wl, device)
+    r = B.dyson_selfconsistent(prob, V, U, J, lam=0.7, delta_sc=1e-12, max_sc=60, tol=1e-14,
+                               max_iter=400)
+    assert r["iterations"] == len(hist)
+    assert abs(r["norm"] - hist[-1]) <= 1e-3 * hist[-1] + 1e-14
+    assert np.abs(_np(r["sigma"]) - sig_ref).max() <= 1e-11 * np.abs(sig_ref).max()
+    n_t = c.n_t
+    G_loc = np.stack([G_ref[i * n_t:(i + 1) * n_t, i * n_t:(i + 1) * n_t] for i in range(wl.n_r)])
+    assert np.abs(_np(r["G_loc"]) - G_loc).max() <= 1e-11 * np.abs(G_loc).max()
+    n, _ = B.local_observables(prob, r["G_loc"], r["G_nn"], J)
+    assert np.abs(_np(n) - O.occupancy(G_loc, c)).max() <= 1e-11

@@ -105,80 +105,101 @@ __device__ void site_phases(const double* U, double eps, Geom g, double* t1r, do
 }
 
 // part(a, b) = - sum_{c,d} K(c,d) [G^II_{up up} + G^II_{up dn}](a, d; c, b):
-// one thread per (a, b), one workgroup per (site, 256 outputs).
+// one thread per (a, b), one workgroup per (site, 256 outputs).  The phase
+// factor an operator at z contributes, exp(i (Theta_after - Theta_before)(z)),
+// is one of four tabulated values (Theta_dn = Theta_up): e^{+-i Theta_1} for
+// 0 <-> 1 particle, e^{+-i (Theta_3 - Theta_1)} for 1 <-> 2 particles, so a
+// path costs four complex products and no transcendental function.  Tables are
+// finite on the imaginary branch (|eps|, |eps + U| times beta stay far from
+// the double range); the Boltzmann weight multiplies the product.
 __global__ __launch_bounds__(kS2Threads)
 void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict__ V,
                         const double* __restrict__ U, double2* __restrict__ out, Geom g) {
     __shared__ double t1r[kMaxNt], t1i[kMaxNt], t3r[kMaxNt], t3i[kMaxNt];
     __shared__ double cum[kMaxNt];
+    __shared__ double2 fac[4][kMaxNt];   // [0] e^{i T1}, [1] e^{-i T1}, [2] e^{i(T3-T1)}, [3] e^{-i(T3-T1)}
     const int site = blockIdx.y;
     const int n_t = g.n_t;
     const double U0 = U[0];
     const double eps = V[site] - 0.5 * U0 - g.mu;
     site_phases(U, eps, g, t1r, t1i, t3r, t3i, cum);
-    // log Boltzmann weights of the four states at t_min
+    for (int z = threadIdx.x; z < n_t; z += kS2Threads) {
+        // exp(i (x + i y)) = e^{-y} (cos x + i sin x)
+        double s, c;
+        sincos(t1r[z], &s, &c);
+        double m = exp(-t1i[z]);
+        fac[0][z] = make_double2(m * c, m * s);
+        m = exp(t1i[z]);
+        fac[1][z] = make_double2(m * c, -m * s);
+        const double dr = t3r[z] - t1r[z], di = t3i[z] - t1i[z];
+        sincos(dr, &s, &c);
+        m = exp(-di);
+        fac[2][z] = make_double2(m * c, m * s);
+        m = exp(di);
+        fac[3][z] = make_double2(m * c, -m * s);
+    }
+    __syncthreads();
+    // Boltzmann weights of the four states at t_min
     const double lw1 = -g.beta * eps, lw3 = -g.beta * (2.0 * eps + U0);
     const double mx = fmax(fmax(0.0, lw1), lw3);
     const double lz = mx + log(exp(-mx) + 2.0 * exp(lw1 - mx) + exp(lw3 - mx));
-    const double lp[4] = {-lz, lw1 - lz, lw1 - lz, lw3 - lz};
+    const double pw[4] = {exp(-lz), exp(lw1 - lz), exp(lw1 - lz), exp(lw3 - lz)};
 
     const int e = blockIdx.x * kS2Threads + threadIdx.x;
     if (e >= n_t * n_t) return;
     const int a = e / n_t, b = e - (e / n_t) * n_t;
     const double2* Ki = K + (size_t)site * n_t * n_t;
-    auto th_re = [&](int st, int z) { return st == 0 ? 0.0 : (st == 3 ? t3r[z] : t1r[z]); };
-    auto th_im = [&](int st, int z) { return st == 0 ? 0.0 : (st == 3 ? t3i[z] : t1i[z]); };
     double acc_r = 0.0, acc_i = 0.0;
     for (int c = 0; c < n_t; ++c) {
         for (int d = 0; d < n_t; ++d) {
             const double2 k = Ki[(size_t)c * n_t + d];
+            // written order: c_up(a), c_s1(d), c^dag_s1(c), c^dag_up(b); the
+            // contour order (stable, descending key) is the same for both spins
+            int slot[4] = {0, 1, 2, 3};
+            int pt[4] = {a, d, c, b};
+            int key[4] = {2 * a, 2 * d, 2 * c + 1, 2 * b + 1};
+            double sgn = 1.0;
+#pragma unroll
+            for (int i = 1; i < 4; ++i) {
+#pragma unroll
+                for (int j = i; j > 0; --j) {
+                    if (key[j] > key[j - 1]) {
+                        int t = key[j]; key[j] = key[j - 1]; key[j - 1] = t;
+                        t = slot[j]; slot[j] = slot[j - 1]; slot[j - 1] = t;
+                        t = pt[j]; pt[j] = pt[j - 1]; pt[j - 1] = t;
+                        sgn = -sgn;
+                    }
+                }
+            }
             double gr = 0.0, gi = 0.0;
 #pragma unroll
             for (int s1 = 0; s1 < 2; ++s1) {
-                // written order: c_up(a), c_s1(d), c^dag_s1(c), c^dag_up(b)
-                int kind[4] = {0, s1 == 0 ? 0 : 1, s1 == 0 ? 2 : 3, 2};
-                int pt[4] = {a, d, c, b};
-                int key[4] = {2 * a, 2 * d, 2 * c + 1, 2 * b + 1};
-                // stable insertion sort, descending key, tracking the parity
-                double sgn = 1.0;
-#pragma unroll
-                for (int i = 1; i < 4; ++i) {
-#pragma unroll
-                    for (int j = i; j > 0; --j) {
-                        if (key[j] > key[j - 1]) {
-                            int t = key[j]; key[j] = key[j - 1]; key[j - 1] = t;
-                            t = kind[j]; kind[j] = kind[j - 1]; kind[j - 1] = t;
-                            t = pt[j]; pt[j] = pt[j - 1]; pt[j - 1] = t;
-                            sgn = -sgn;
-                        }
-                    }
-                }
-                // trace over initial states: apply the ordered product right to left
+                // operator kind of each written slot for this spin
+                const int kind_of[4] = {0, s1 == 0 ? 0 : 1, s1 == 0 ? 2 : 3, 2};
 #pragma unroll
                 for (int nu = 0; nu < 4; ++nu) {
                     int st = nu;
-                    double amp = sgn;
-                    double xr = lp[nu], xi = 0.0;     // exponent of the path
+                    double amp = sgn * pw[nu];
+                    double2 f = make_double2(1.0, 0.0);
 #pragma unroll
-                    for (int q = 3; q >= 0 && st >= 0; --q) {
-                        const int nx = kNext[kind[q]][st];
+                    for (int q = 3; q >= 0; --q) {
+                        const int kind = kind_of[slot[q]];
+                        const int nx = kNext[kind][st];
                         if (nx < 0) {
-                            st = -1;
+                            amp = 0.0;
                             break;
                         }
-                        amp *= kAmp[kind[q]][st];
-                        // exp(i (Theta_nx - Theta_st)(z)) = exp(-dIm + i dRe)
-                        const int z = pt[q];
-                        xr -= th_im(nx, z) - th_im(st, z);
-                        xi += th_re(nx, z) - th_re(st, z);
+                        amp *= kAmp[kind][st];
+                        // particle number goes up (creation) or down; which table
+                        const int up = kind >= 2;
+                        const int two = (st == 3 || nx == 3);
+                        f = cmul2(f, fac[(two ? 2 : 0) + (up ? 0 : 1)][pt[q]]);
                         st = nx;
                     }
-                    if (st != nu) continue;
-                    double s, co;
-                    sincos(xi, &s, &co);
-                    const double m = amp * exp(xr);
-                    gr += m * co;
-                    gi += m * s;
+                    if (amp != 0.0 && st == nu) {
+                        gr += amp * f.x;
+                        gi += amp * f.y;
+                    }
                 }
             }
             // G^II carries (-i)^2 = -1; part = - K G^II = + K (gr + i gi)

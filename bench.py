@@ -61,8 +61,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
                     help="skip the time-to-solution and adjoint legs (profiling runs)")
-    ap.add_argument("--legs", default="fp64,mixed,sym,gmres,adjoint",
-                    help="comma list of extra legs: fp64, mixed, sym, gmres, adjoint")
+    ap.add_argument("--legs", default="fp64,mixed,sym,gmres,selfenergy,adjoint",
+                    help="comma list of extra legs: fp64, mixed, sym, gmres, selfenergy, adjoint")
     ap.add_argument("--gmres-restart", type=int, default=6)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -141,6 +141,48 @@ def gmres_leg(B, prob, S, V, U, J, src, block, n_ref, restart):
             "workspace_GB": round(ws.numel() / 1e9, 1)}
     del ws
     torch.cuda.empty_cache()
+    return out
+
+
+def selfenergy_leg(B, prob, S, V, U, J, G_loc, wl):
+    """Second-order self-energy (Sec. III): one Sigma~ evaluation of all sites of
+    the workload from the local G of its lowest-order solve (the N_t^4
+    contraction, FP64 on the vector units) and the dressed blocks; then the
+    whole self-consistent loop (lam 0.7, delta_sc 1e-8) on the 12x12 trap."""
+    import torch
+    out = {}
+    ws = torch.empty(B.sigma2_workspace_bytes(prob), dtype=torch.uint8, device=S.device)
+    sig = torch.empty_like(S)
+    Sd = torch.empty_like(S)
+    for rep in range(2):              # first repetition warms up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.sigma2_build(prob, V, U, J, S, G_loc, out=sig, ws=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.sigma2_dress(prob, S, sig, out=Sd, ws=ws)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+    quads = wl.n_r * wl.n_t ** 4
+    out["sigma2_build_ms"] = round(1e3 * (t1 - t0), 2)
+    out["quadruples_per_s"] = quads / (t1 - t0)
+    out["dress_ms"] = round(1e3 * (t2 - t1), 2)
+    out["sigma_abs_max"] = float(sig.abs().max())
+    del ws, sig, Sd
+    wl4 = W.config(4)
+    p4 = B.problem_from_workload(wl4)
+    V4 = torch.tensor(wl4.V, dtype=torch.float64, device=S.device)
+    U4 = torch.tensor(wl4.U, dtype=torch.float64, device=S.device)
+    J4 = torch.tensor(wl4.J, dtype=torch.float64, device=S.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = B.dyson_selfconsistent(p4, V4, U4, J4, lam=0.7, delta_sc=1e-8, max_sc=60, tol=1e-12)
+    torch.cuda.synchronize()
+    n0, _ = B.local_observables(p4, r["G_loc"], r["G_nn"], J4)
+    out[f"selfconsistent_{wl4.name}"] = {"seconds": round(time.perf_counter() - t0, 3),
+                                         "steps": r["iterations"], "norm": r["norm"],
+                                         "dyson_sweeps": r["stats"]["sweeps_total"],
+                                         "n_centre_t0": float(n0[wl4.n_r // 2, 0])}
     return out
 
 
@@ -304,6 +346,8 @@ def main():
             tts[label]["sources_solved"] = orbit_count(wl.Lx, wl.Ly)
     if "gmres" in want:
         tts.update(gmres_leg(B, prob, S, V, U, J, src, block, n_ref, args.gmres_restart))
+    if "selfenergy" in want:
+        rec["selfenergy"] = selfenergy_leg(B, prob, S, V, U, J, outs["G_loc"], wl)
     if tts:
         rec["time_to_solution"] = tts
     if "adjoint" in want:

@@ -24,6 +24,9 @@
 // The dressed block (the contour inverse of calG^-1 - Sigma, with
 // Sigma = calG^-1 o Sigma~ o calG^-1) is S' = S (S - Sigma~)^-1 S in plain
 // matrices; the lattice solve with S' in place of S is eq. Glatt with Sigma.
+#include <algorithm>
+#include <cstring>
+
 #include "internal.h"
 
 namespace scd {
@@ -38,8 +41,78 @@ __device__ inline double2 cmul2(double2 a, double2 b) {
 // Transitions of the four operators c_up, c_dn, c^dag_up, c^dag_dn on the
 // states 0 |0>, 1 |dn>, 2 |up>, 3 |up dn> = c^dag_up c^dag_dn |0>:
 // next state (-1: annihilated) and sign.
-__constant__ int kNext[4][4] = {{-1, -1, 0, 1}, {-1, 0, -1, 2}, {2, 3, -1, -1}, {1, -1, 3, -1}};
-__constant__ double kAmp[4][4] = {{0, 0, 1, 1}, {0, 1, 0, -1}, {1, 1, 0, 0}, {1, 0, -1, 0}};
+constexpr int kNext[4][4] = {{-1, -1, 0, 1}, {-1, 0, -1, 2}, {2, 3, -1, -1}, {1, -1, 3, -1}};
+constexpr int kAmp[4][4] = {{0, 0, 1, 1}, {0, 1, 0, -1}, {1, 1, 0, 0}, {1, 0, -1, 0}};
+
+// The contour order of the four operators c_up(a), c_s1(d), c^dag_s1(c),
+// c^dag_up(b) (written slots 0..3) is one of 24 permutations, fixed by the six
+// pairwise key comparisons; for each permutation and neighbour spin the
+// number-state paths that survive the ordered product are fixed too.  Per
+// path: the initial state, the amplitude (transition signs times the
+// permutation's sign) and, per written slot, which phase table its operator
+// uses (0: e^{i T1}, 1: e^{-i T1}, 2: e^{i (T3 - T1)}, 3: e^{-i (T3 - T1)}).
+struct PathTable {
+    signed char perm_of[64];          // comparison bits -> permutation
+    signed char npath[24][2];
+    signed char nu[24][2][4];
+    signed char amp[24][2][4];
+    signed char tab[24][2][4][4];     // [perm][spin][path][written slot]
+};
+
+PathTable build_path_table() {
+    PathTable T;
+    std::memset(&T, 0, sizeof T);
+    std::memset(T.perm_of, -1, sizeof T.perm_of);
+    int order[4] = {0, 1, 2, 3};
+    int p = 0;
+    do {
+        int rank[4];
+        for (int q = 0; q < 4; ++q) rank[order[q]] = q;
+        // bit for written pair (i, j), i < j: j precedes i in contour order
+        const int pairs[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+        int code = 0, inv = 0;
+        for (int k = 0; k < 6; ++k) {
+            const int i = pairs[k][0], j = pairs[k][1];
+            if (rank[j] < rank[i]) {
+                code |= 1 << k;
+                ++inv;
+            }
+        }
+        T.perm_of[code] = (signed char)p;
+        const int sign = (inv & 1) ? -1 : 1;
+        for (int s1 = 0; s1 < 2; ++s1) {
+            const int kind_of[4] = {0, s1 == 0 ? 0 : 1, s1 == 0 ? 2 : 3, 2};
+            int n = 0;
+            for (int nu = 0; nu < 4; ++nu) {
+                int st = nu, amp = sign;
+                int tabs[4] = {0, 0, 0, 0};
+                bool ok = true;
+                for (int q = 3; q >= 0; --q) {          // rightmost operator acts first
+                    const int slot = order[q];
+                    const int kind = kind_of[slot];
+                    const int nx = kNext[kind][st];
+                    if (nx < 0) {
+                        ok = false;
+                        break;
+                    }
+                    amp *= kAmp[kind][st];
+                    const bool creation = kind >= 2;
+                    const bool two = st == 3 || nx == 3;
+                    tabs[slot] = (two ? 2 : 0) + (creation ? 0 : 1);
+                    st = nx;
+                }
+                if (!ok || st != nu) continue;
+                T.nu[p][s1][n] = (signed char)nu;
+                T.amp[p][s1][n] = (signed char)amp;
+                for (int w = 0; w < 4; ++w) T.tab[p][s1][n][w] = (signed char)tabs[w];
+                ++n;
+            }
+            T.npath[p][s1] = (signed char)n;
+        }
+        ++p;
+    } while (std::next_permutation(order, order + 4));
+    return T;
+}
 
 // K_i = diag(wJ) (sum of the neighbours' G_loc) diag(wJ), one thread per element.
 __global__ __launch_bounds__(256)
@@ -108,16 +181,25 @@ __device__ void site_phases(const double* U, double eps, Geom g, double* t1r, do
 // one thread per (a, b), one workgroup per (site, 256 outputs).  The phase
 // factor an operator at z contributes, exp(i (Theta_after - Theta_before)(z)),
 // is one of four tabulated values (Theta_dn = Theta_up): e^{+-i Theta_1} for
-// 0 <-> 1 particle, e^{+-i (Theta_3 - Theta_1)} for 1 <-> 2 particles, so a
-// path costs four complex products and no transcendental function.  Tables are
-// finite on the imaginary branch (|eps|, |eps + U| times beta stay far from
-// the double range); the Boltzmann weight multiplies the product.
+// 0 <-> 1 particle, e^{+-i (Theta_3 - Theta_1)} for 1 <-> 2 particles.  Six
+// key comparisons give the contour order's permutation, whose surviving
+// number-state paths come from the path table (LDS), so a path costs four
+// table reads and three complex products.  The tables are finite on the
+// imaginary branch (|eps|, |eps + U| times beta stay far from the double
+// range); the Boltzmann weight multiplies the product.
 __global__ __launch_bounds__(kS2Threads)
 void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict__ V,
-                        const double* __restrict__ U, double2* __restrict__ out, Geom g) {
+                        const double* __restrict__ U, double2* __restrict__ out, Geom g,
+                        PathTable paths) {
     __shared__ double t1r[kMaxNt], t1i[kMaxNt], t3r[kMaxNt], t3i[kMaxNt];
     __shared__ double cum[kMaxNt];
     __shared__ double2 fac[4][kMaxNt];   // [0] e^{i T1}, [1] e^{-i T1}, [2] e^{i(T3-T1)}, [3] e^{-i(T3-T1)}
+    __shared__ PathTable tb;
+    {
+        const signed char* src = reinterpret_cast<const signed char*>(&paths);
+        signed char* dst = reinterpret_cast<signed char*>(&tb);
+        for (int k = threadIdx.x; k < (int)sizeof(PathTable); k += kS2Threads) dst[k] = src[k];
+    }
     const int site = blockIdx.y;
     const int n_t = g.n_t;
     const double U0 = U[0];
@@ -149,57 +231,31 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     if (e >= n_t * n_t) return;
     const int a = e / n_t, b = e - (e / n_t) * n_t;
     const double2* Ki = K + (size_t)site * n_t * n_t;
+    // keys of the written slots: later contour point first, a creation
+    // operator later than an annihilation operator at the same point
+    const int ka = 2 * a, kb = 2 * b + 1;
     double acc_r = 0.0, acc_i = 0.0;
     for (int c = 0; c < n_t; ++c) {
+        const int kc = 2 * c + 1;
+        const int code_c = ((kc > ka) << 1) | ((kb > ka) << 2) | ((kb > kc) << 5);
         for (int d = 0; d < n_t; ++d) {
             const double2 k = Ki[(size_t)c * n_t + d];
-            // written order: c_up(a), c_s1(d), c^dag_s1(c), c^dag_up(b); the
-            // contour order (stable, descending key) is the same for both spins
-            int slot[4] = {0, 1, 2, 3};
-            int pt[4] = {a, d, c, b};
-            int key[4] = {2 * a, 2 * d, 2 * c + 1, 2 * b + 1};
-            double sgn = 1.0;
-#pragma unroll
-            for (int i = 1; i < 4; ++i) {
-#pragma unroll
-                for (int j = i; j > 0; --j) {
-                    if (key[j] > key[j - 1]) {
-                        int t = key[j]; key[j] = key[j - 1]; key[j - 1] = t;
-                        t = slot[j]; slot[j] = slot[j - 1]; slot[j - 1] = t;
-                        t = pt[j]; pt[j] = pt[j - 1]; pt[j - 1] = t;
-                        sgn = -sgn;
-                    }
-                }
-            }
+            const int kd = 2 * d;
+            const int code = code_c | (kd > ka) | ((kc > kd) << 3) | ((kb > kd) << 4);
+            const int p = tb.perm_of[code];
+            const int tpt[4] = {a, d, c, b};
             double gr = 0.0, gi = 0.0;
 #pragma unroll
             for (int s1 = 0; s1 < 2; ++s1) {
-                // operator kind of each written slot for this spin
-                const int kind_of[4] = {0, s1 == 0 ? 0 : 1, s1 == 0 ? 2 : 3, 2};
-#pragma unroll
-                for (int nu = 0; nu < 4; ++nu) {
-                    int st = nu;
-                    double amp = sgn * pw[nu];
-                    double2 f = make_double2(1.0, 0.0);
-#pragma unroll
-                    for (int q = 3; q >= 0; --q) {
-                        const int kind = kind_of[slot[q]];
-                        const int nx = kNext[kind][st];
-                        if (nx < 0) {
-                            amp = 0.0;
-                            break;
-                        }
-                        amp *= kAmp[kind][st];
-                        // particle number goes up (creation) or down; which table
-                        const int up = kind >= 2;
-                        const int two = (st == 3 || nx == 3);
-                        f = cmul2(f, fac[(two ? 2 : 0) + (up ? 0 : 1)][pt[q]]);
-                        st = nx;
-                    }
-                    if (amp != 0.0 && st == nu) {
-                        gr += amp * f.x;
-                        gi += amp * f.y;
-                    }
+                const int np = tb.npath[p][s1];
+                for (int q = 0; q < np; ++q) {
+                    const signed char* tq = tb.tab[p][s1][q];
+                    double2 f = cmul2(fac[tq[0]][tpt[0]], fac[tq[1]][tpt[1]]);
+                    f = cmul2(f, fac[tq[2]][tpt[2]]);
+                    f = cmul2(f, fac[tq[3]][tpt[3]]);
+                    const double w = tb.amp[p][s1][q] * pw[tb.nu[p][s1][q]];
+                    gr += w * f.x;
+                    gi += w * f.y;
                 }
             }
             // G^II carries (-i)^2 = -1; part = - K G^II = + K (gr + i gi)
@@ -403,7 +459,8 @@ hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const 
                          double2* sig, hipStream_t st) {
     hipLaunchKernelGGL(k_build_kernel, dim3(2048), dim3(256), 0, st, G_loc_all, J, K, g);
     const dim3 grid((g.n_t * g.n_t + kS2Threads - 1) / kS2Threads, g.n_r);
-    hipLaunchKernelGGL(sigma2_pair_kernel, grid, dim3(kS2Threads), 0, st, K, V, U, part, g);
+    static const PathTable paths = build_path_table();
+    hipLaunchKernelGGL(sigma2_pair_kernel, grid, dim3(kS2Threads), 0, st, K, V, U, part, g, paths);
     hipLaunchKernelGGL(sigma2_onebody_kernel, grid, dim3(kS2Threads), 0, st, S, K, part, sig, g);
     return hipGetLastError();
 }

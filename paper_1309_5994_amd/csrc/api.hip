@@ -1012,7 +1012,7 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
 namespace {
 
 struct S2Layout {
-    size_t off_k, off_part, off_aug, off_flag, total;
+    size_t off_k, off_part, off_m, off_aug, off_flag, total;
 };
 
 S2Layout s2_layout(const Geom& g) {
@@ -1026,6 +1026,7 @@ S2Layout s2_layout(const Geom& g) {
     const size_t blocks = (size_t)g.n_r * g.n_t * g.n_t * sizeof(double2);
     L.off_k = take(blocks);
     L.off_part = take(blocks);
+    L.off_m = take(blocks);
     L.off_aug = take(2 * blocks);
     L.off_flag = take(sizeof(int));
     L.total = off;
@@ -1059,7 +1060,7 @@ int sigma2_build(const scd_problem* p, const double* V, const double* U, const d
     char* base = (char*)ws;
     SCD_HIP(launch_sigma2(g, V, U, J, (const double2*)S, (const double2*)G_loc_all,
                           (double2*)(base + L.off_k), (double2*)(base + L.off_part),
-                          (double2*)sig_out, st),
+                          (double2*)(base + L.off_m), (double2*)sig_out, st),
             "sigma2 launch");
     g_last_error.clear();
     return SCD_OK;

@@ -145,7 +145,7 @@ hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf
 // ---- second-order self-energy (sigma2.hip) ----
 hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const double* J,
                          const double2* S, const double2* G_loc_all, double2* K, double2* part,
-                         double2* sig, hipStream_t st);
+                         double2* M, double2* sig, hipStream_t st);
 hipError_t launch_dress(const Geom& g, const double2* S, const double2* sig, double2* aug,
                         double2* S_out, int* singular, hipStream_t st);
 // sig <- lam fresh + (1 - lam) sig; part[2 w] = sum |fresh - sig|^2, part[2 w + 1] =

@@ -266,10 +266,32 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);
 }
 
-// Sigma~ = part + 2 S(a,b) T - (S K S)(a,b), T = sum_{c,d} K(c,d) S(d,c): one
-// workgroup per (site, 256 outputs), T reduced inside each workgroup.
+// M = K S per site (one thread per (c, b)), the first factor of the
+// cumulant's one-particle term S K S.
 __global__ __launch_bounds__(kS2Threads)
-void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restrict__ K,
+void ks_kernel(const double2* __restrict__ S, const double2* __restrict__ K,
+               double2* __restrict__ M, Geom g) {
+    const int site = blockIdx.y;
+    const int n_t = g.n_t;
+    const size_t per = (size_t)n_t * n_t;
+    const int e = blockIdx.x * kS2Threads + threadIdx.x;
+    if (e >= n_t * n_t) return;
+    const int c = e / n_t, b = e - (e / n_t) * n_t;
+    const double2* Si = S + (size_t)site * per;
+    const double2* Ki = K + (size_t)site * per;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int d = 0; d < n_t; ++d) {
+        const double2 v = cmul2(Ki[(size_t)c * n_t + d], Si[(size_t)d * n_t + b]);
+        acc.x += v.x;
+        acc.y += v.y;
+    }
+    M[(size_t)site * per + e] = acc;
+}
+
+// Sigma~ = part + 2 S(a,b) T - (S M)(a,b), T = sum_{c,d} K(c,d) S(d,c) = trace(M):
+// one workgroup per (site, 256 outputs), T reduced inside each workgroup.
+__global__ __launch_bounds__(kS2Threads)
+void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restrict__ M,
                            const double2* __restrict__ part, double2* __restrict__ sig,
                            Geom g) {
     __shared__ double red_r[kS2Threads], red_i[kS2Threads];
@@ -277,13 +299,11 @@ void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restr
     const int n_t = g.n_t;
     const size_t per = (size_t)n_t * n_t;
     const double2* Si = S + (size_t)site * per;
-    const double2* Ki = K + (size_t)site * per;
+    const double2* Mi = M + (size_t)site * per;
     double tr = 0.0, ti = 0.0;
-    for (int cd = threadIdx.x; cd < n_t * n_t; cd += kS2Threads) {
-        const int c = cd / n_t, d = cd - (cd / n_t) * n_t;
-        const double2 v = cmul2(Ki[cd], Si[(size_t)d * n_t + c]);
-        tr += v.x;
-        ti += v.y;
+    for (int c = threadIdx.x; c < n_t; c += kS2Threads) {
+        tr += Mi[(size_t)c * n_t + c].x;
+        ti += Mi[(size_t)c * n_t + c].y;
     }
     red_r[threadIdx.x] = tr;
     red_i[threadIdx.x] = ti;
@@ -299,16 +319,9 @@ void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restr
     const int e = blockIdx.x * kS2Threads + threadIdx.x;
     if (e >= n_t * n_t) return;
     const int a = e / n_t, b = e - (e / n_t) * n_t;
-    // (S K S)(a, b) = sum_c S(a,c) sum_d K(c,d) S(d,b)
     double2 sks = make_double2(0.0, 0.0);
     for (int c = 0; c < n_t; ++c) {
-        double2 inner = make_double2(0.0, 0.0);
-        for (int d = 0; d < n_t; ++d) {
-            const double2 v = cmul2(Ki[(size_t)c * n_t + d], Si[(size_t)d * n_t + b]);
-            inner.x += v.x;
-            inner.y += v.y;
-        }
-        const double2 v = cmul2(Si[(size_t)a * n_t + c], inner);
+        const double2 v = cmul2(Si[(size_t)a * n_t + c], Mi[(size_t)c * n_t + b]);
         sks.x += v.x;
         sks.y += v.y;
     }
@@ -456,12 +469,13 @@ hipError_t launch_mix(const double2* fresh, double2* sig, double lam, size_t n, 
 
 hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const double* J,
                          const double2* S, const double2* G_loc_all, double2* K, double2* part,
-                         double2* sig, hipStream_t st) {
+                         double2* M, double2* sig, hipStream_t st) {
     hipLaunchKernelGGL(k_build_kernel, dim3(2048), dim3(256), 0, st, G_loc_all, J, K, g);
     const dim3 grid((g.n_t * g.n_t + kS2Threads - 1) / kS2Threads, g.n_r);
     static const PathTable paths = build_path_table();
     hipLaunchKernelGGL(sigma2_pair_kernel, grid, dim3(kS2Threads), 0, st, K, V, U, part, g, paths);
-    hipLaunchKernelGGL(sigma2_onebody_kernel, grid, dim3(kS2Threads), 0, st, S, K, part, sig, g);
+    hipLaunchKernelGGL(ks_kernel, grid, dim3(kS2Threads), 0, st, S, K, M, g);
+    hipLaunchKernelGGL(sigma2_onebody_kernel, grid, dim3(kS2Threads), 0, st, S, M, part, sig, g);
     return hipGetLastError();
 }
 

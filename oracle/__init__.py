@@ -44,7 +44,8 @@ from .contour import Contour, make_contour
 from .atomic import atomic_gf, atomic_gf_fock, boltzmann_weights, level_phases
 from .lattice import neighbours, hopping_on_contour, hopping_operator_dense
 from .dyson import (blockdiag, dyson_dense, dyson_columns_blocktri,
-                    neumann_partial_sums, dense_system_matrix)
+                    neumann_partial_sums, dense_system_matrix, dyson_columns_truncated,
+                    lattice_distance)
 from .gmres import gmres_column, gmres_dense
 from . import selfenergy
 from .observables import (occupancy, kinetic_energy, double_occupancy,
@@ -59,6 +60,7 @@ __all__ = [
     "neighbours", "hopping_on_contour", "hopping_operator_dense",
     "blockdiag", "dyson_dense", "dyson_columns_blocktri",
     "neumann_partial_sums", "dense_system_matrix", "gmres_column", "gmres_dense",
+    "dyson_columns_truncated", "lattice_distance",
     "occupancy", "kinetic_energy", "double_occupancy", "doubly_occupied_fraction",
     "extrapolate_dt", "loss_and_grad_dense", "loss_dense",
     "site_levels", "atomic_gf_derivatives",

@@ -22,6 +22,8 @@ exactly:
                                 matrix couples row x only to rows x +- 1).
 * ``neumann_partial_sums``   -- X_n = sum_{nu <= n} (S D)^nu S X restricted to
                                 chosen columns, for the Dyson-series pins.
+* ``dyson_columns_truncated`` -- the columns of each source solved on the
+                                sites within a lattice distance of it only.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -151,4 +153,32 @@ def neumann_partial_sums(S_blocks: np.ndarray, D: np.ndarray, cols, n_terms: int
     for _ in range(n_terms):
         x = x0 + SD @ x
         out.append(x)
+    return out
+
+
+def lattice_distance(i: int, j: int, Lx: int, Ly: int, periodic: bool = False) -> int:
+    """Manhattan distance between sites i = x * Ly + y and j (minimum image if periodic)."""
+    dx, dy = abs(i // Ly - j // Ly), abs(i % Ly - j % Ly)
+    if periodic:
+        dx, dy = min(dx, Lx - dx), min(dy, Ly - dy)
+    return dx + dy
+
+
+def dyson_columns_truncated(S_blocks: np.ndarray, D: np.ndarray, Lx: int, Ly: int,
+                            periodic: bool, src_sites, radius: int) -> np.ndarray:
+    """Columns of each source j solved on the sites within lattice distance
+    `radius` of j only: the Dyson equation restricted to those sites (App. C:
+    only blocks near the source matter), G zero elsewhere.  Shape
+    (N_r, N_t, len(src_sites) * N_t)."""
+    n_r, n_t, _ = S_blocks.shape
+    S = blockdiag(S_blocks)
+    out = np.zeros((n_r, n_t, len(src_sites) * n_t), dtype=np.complex128)
+    for s, j in enumerate(src_sites):
+        keep = [i for i in range(n_r) if lattice_distance(i, j, Lx, Ly, periodic) <= radius]
+        idx = np.concatenate([np.arange(i * n_t, (i + 1) * n_t) for i in keep])
+        A = np.eye(len(idx), dtype=np.complex128) - S[np.ix_(idx, idx)] @ D[np.ix_(idx, idx)]
+        rhs = S[idx, j * n_t:(j + 1) * n_t]
+        sol = np.linalg.solve(A, rhs)
+        for k, i in enumerate(keep):
+            out[i, :, s * n_t:(s + 1) * n_t] = sol[k * n_t:(k + 1) * n_t]
     return out

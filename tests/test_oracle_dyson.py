@@ -174,3 +174,25 @@ def test_blocktridiagonal_columns_equal_dense(Lx, Ly, periodic_y):
     ref = O.dyson_dense(S, D, cols=cols).reshape(wl.n_r, n_t, len(src) * n_t)
     got = O.dyson_columns_blocktri(S, Lx, Ly, wl.J, c, src, periodic_y=periodic_y)
     assert np.abs(got - ref).max() < 1e-13
+
+
+def test_truncated_columns():
+    """Far-block truncation: radius 0 keeps only S_j; a radius covering the
+    lattice is the full solve; the error to the full solve falls off
+    geometrically with the radius (G decays with distance)."""
+    wl = W.custom(5, 4, 4, 4, J0=0.1, seed=13)
+    c, S, D = _setup(wl)
+    src = [0, 7, 13]
+    n_t = c.n_t
+    full = O.dyson_dense(S, D, [j * n_t + b for j in src for b in range(n_t)])
+    full = full.reshape(wl.n_r, n_t, len(src) * n_t)
+    t0 = O.dyson_columns_truncated(S, D, wl.Lx, wl.Ly, False, src, 0)
+    for s, j in enumerate(src):
+        assert np.abs(t0[j, :, s * n_t:(s + 1) * n_t] - S[j]).max() == 0.0
+        others = [i for i in range(wl.n_r) if i != j]
+        assert np.abs(t0[others, :, s * n_t:(s + 1) * n_t]).max() == 0.0
+    big = O.dyson_columns_truncated(S, D, wl.Lx, wl.Ly, False, src, wl.Lx + wl.Ly)
+    assert np.abs(big - full).max() < 1e-14
+    errs = [np.abs(O.dyson_columns_truncated(S, D, wl.Lx, wl.Ly, False, src, r) - full).max()
+            for r in range(1, 6)]
+    assert all(errs[k + 1] < 0.3 * errs[k] for k in range(len(errs) - 1))

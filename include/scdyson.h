@@ -184,6 +184,24 @@ int dyson_iterate_sym(const scd_problem* p, const void* S, const double* J,
                       void* ws, size_t ws_bytes, scd_stats* st, void* stream);
 
 /*
+ * dyson_iterate (FP64) with the far blocks truncated: the columns of source j
+ * are solved on the sites within lattice distance max_radius of j only (the
+ * Dyson equation restricted to those sites; G is zero beyond).  G decays with
+ * the distance from the source (about a decade per two hops on the 16x16
+ * trap), so a radius whose outer blocks lie below the accuracy wanted
+ * (App. C: only blocks in the spatial vicinity of the source matter) saves
+ * the sweeps' work on the far (target, source) pairs.  max_radius >= the
+ * lattice diameter reproduces dyson_iterate exactly.  Workspace as
+ * scd_workspace_bytes(..., SCD_PREC_FP64); other arguments and errors as
+ * dyson_iterate.
+ */
+int dyson_iterate_trunc(const scd_problem* p, const void* S, const double* J,
+                        const int32_t* src, int32_t n_src, int32_t block_sites,
+                        int32_t max_radius, double tol, int32_t max_iter,
+                        void* G_cols, void* G_loc, void* G_nn,
+                        void* ws, size_t ws_bytes, scd_stats* st, void* stream);
+
+/*
  * Device workspace (bytes) that dyson_gmres needs for n_src source sites in
  * column blocks of block_sites sources with `restart` Krylov vectors per cycle.
  * Returns SCD_OK and writes *bytes, or SCD_EINVAL.

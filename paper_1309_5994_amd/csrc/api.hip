@@ -244,7 +244,9 @@ struct Solver {
     }
     // Algorithmic flops of a launch whose output reaches lattice distance
     // `radius` on the targets of `which` (0 all, 1 even, 2 odd colour).
+    int trunc = -1;    // truncation radius of the solve, or -1
     double sweep_flops(int radius, int cols_per_src, int which = 0) const {
+        if (trunc >= 0 && radius > trunc) radius = trunc;
         const std::vector<double>& w = within[which];
         const size_t last = w.size() - 1;
         const double pairs = w[(size_t)radius < last ? (size_t)radius : last];
@@ -808,7 +810,7 @@ int sym_plan(const Geom& g, const int32_t* src, int n_src, int block_sites, size
 int iterate_impl(const scd_problem* p, const void* S, const double* J, const int32_t* src,
                  int32_t n_src, int32_t block_sites, int32_t prec, double tol, int32_t max_iter,
                  void* G_cols, void* G_loc, void* G_nn, void* ws, size_t ws_bytes,
-                 scd_stats* st_out, void* stream, bool sym) {
+                 scd_stats* st_out, void* stream, bool sym, int max_radius = -1) {
     const auto t_start = std::chrono::steady_clock::now();
     scd_stats stats;
     std::memset(&stats, 0, sizeof stats);
@@ -834,6 +836,8 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
     for (int s = 0; s < n_src; ++s)
         if (src[s] < 0 || src[s] >= g.n_r)
             return finish(fail(SCD_EINVAL, "src[%d] = %d outside [0, %d)", s, src[s], g.n_r));
+    if (max_radius >= 0 && prec != SCD_PREC_FP64)
+        return finish(fail(SCD_EINVAL, "truncation is implemented for SCD_PREC_FP64 only"));
     SymPlan plan;
     const int32_t* solve_src = src;
     int n_solve = n_src;
@@ -906,6 +910,7 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
     sv.partial = (double*)(base + L.off_partial);
     sv.slot = (unsigned long long*)(base + L.off_slot);
     sv.nwg = L.nwg;
+    sv.trunc = max_radius;
     int* src_dev = (int*)(base + L.off_src);
 
     SCD_HIP(hipMemcpyAsync(src_dev, solve_src, (size_t)n_solve * sizeof(int32_t),
@@ -951,6 +956,7 @@ int iterate_impl(const scd_problem* p, const void* S, const double* J, const int
         a.group = site_group(g);
         a.x0_kind = X0_BLOCK;
         a.x0_fixed = 0;
+        a.max_radius = max_radius;
         a.sites = nullptr;
         a.n_sites = g.n_r;
         a.part_off = 0;
@@ -1279,6 +1285,15 @@ int dyson_iterate_sym(const scd_problem* p, const void* S, const double* J, cons
                       size_t ws_bytes, scd_stats* st_out, void* stream) {
     return iterate_impl(p, S, J, src, n_src, block_sites, prec, tol, max_iter, G_cols, G_loc, G_nn,
                         ws, ws_bytes, st_out, stream, true);
+}
+
+int dyson_iterate_trunc(const scd_problem* p, const void* S, const double* J, const int32_t* src,
+                        int32_t n_src, int32_t block_sites, int32_t max_radius, double tol,
+                        int32_t max_iter, void* G_cols, void* G_loc, void* G_nn, void* ws,
+                        size_t ws_bytes, scd_stats* st_out, void* stream) {
+    if (max_radius < 0) return fail(SCD_EINVAL, "max_radius must be >= 0");
+    return iterate_impl(p, S, J, src, n_src, block_sites, SCD_PREC_FP64, tol, max_iter, G_cols,
+                        G_loc, G_nn, ws, ws_bytes, st_out, stream, false, max_radius);
 }
 
 int scd_sym_workspace_bytes(const scd_problem* p, const int32_t* src, int32_t n_src,

@@ -53,6 +53,8 @@ struct SweepArgs {
                            // correction sweeps), or nullptr
     int no_x0 = 0;         // SOLVE: leave out X0, Y = St^T N(X) (the batched matvec of GMRES)
     int out_f64 = 0;       // RESIDUAL: write R as complex128 instead of complex64
+    int max_radius = -1;   // SOLVE: truncation radius (lattice distance from a column's
+                           // source beyond which G is zero), or -1
 };
 
 // X0 of a column block (the preconditioned unit-vector bundle):

@@ -44,7 +44,9 @@
 //
 // Modes:
 //  * SOLVE     (FP64): X0 from S (or none: the matvec St^T N(X) of GMRES);
-//              writes Y; partials max|Y - X|, max|Y|.
+//              writes Y; partials max|Y - X|, max|Y|.  With a truncation
+//              radius, columns whose source is farther from the target stay
+//              zero (the Dyson equation restricted to the sites within it).
 //  * RESIDUAL  (FP64): X0 from S; writes R = Y - X as complex64 (the FP64
 //              residual of iterative refinement) or complex128 (the residual
 //              GMRES restarts from); partials max|R|, max|Y|.
@@ -324,6 +326,20 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
     constexpr int NOUT = NOWN + ((SHARED && GRP == 0) ? 1 : 0);
     const int col = n0 + wc * 16 + l16;
     const int s_src = col / cols_per_src;
+    // Truncation: a column whose source is farther than max_radius from the
+    // target stays zero (a tile can hold columns of two sources).
+    bool cut = false;
+    if (MODE == MODE_SOLVE && g.max_radius >= 0 && s_src < g.bs) {
+        const int j = src_blk[s_src];
+        int dx = i / g.Ly - j / g.Ly, dy = i % g.Ly - j % g.Ly;
+        dx = dx < 0 ? -dx : dx;
+        dy = dy < 0 ? -dy : dy;
+        if (g.periodic) {
+            dx = dx < g.Lx - dx ? dx : g.Lx - dx;
+            dy = dy < g.Ly - dy ? dy : g.Ly - dy;
+        }
+        cut = dx + dy > g.max_radius;
+    }
     const int bcol = col - s_src * cols_per_src;
     const bool own =
         (MODE != MODE_CORRECT) && !g.no_x0 && (s_src < g.bs) && (src_blk[s_src] == i);
@@ -354,6 +370,10 @@ __device__ __forceinline__ void sweep_rows(const typename E::cplx* __restrict__ 
                 mabs = fmax(mabs, (double)fmaxf(fabsf(yr), fabsf(yi)));
                 if (!(isfinite(yr) && isfinite(yi))) bad = 1.0;
             } else {
+                if (cut) {
+                    re = 0.0;
+                    im = 0.0;
+                }
                 if (own && row < g.n_t) {
                     dvec2 s0;
                     if (g.x0_kind == X0_COL_T)
@@ -450,7 +470,7 @@ void sweep_kernel(const typename E::cplx* __restrict__ St, const dvec2* __restri
             }
             dmin = dmin < dx + dy ? dmin : dx + dy;
         }
-        if (s_lo >= g.bs || dmin > g.lc_sweep + 1) {
+        if (s_lo >= g.bs || dmin > g.lc_sweep + 1 || (g.max_radius >= 0 && dmin > g.max_radius)) {
             if (tid < 3) part[3 * blockIdx.x + tid] = 0.0;
             return;
         }

@@ -86,6 +86,11 @@ def lib():
     L.dyson_iterate.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                 _vp, _vp, _vp, _vp, ctypes.c_size_t, _P(Stats), _vp]
+    L.dyson_iterate_trunc.restype = ctypes.c_int
+    L.dyson_iterate_trunc.argtypes = [_P(Problem), _vp, _vp, _P(ctypes.c_int32), ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                      _P(Stats), _vp]
     L.scd_sym_workspace_bytes.restype = ctypes.c_int
     L.scd_sym_workspace_bytes.argtypes = [_P(Problem), _P(ctypes.c_int32), ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, _P(ctypes.c_size_t)]
@@ -234,6 +239,32 @@ def dyson_iterate(prob: Problem, S, J, src, block_sites=None, prec=PREC_FP64, to
                              float(tol), int(max_iter), _ptr(G_cols), _ptr(G_loc), _ptr(G_nn),
                              _ptr(ws), ctypes.c_size_t(ws.numel()), ctypes.byref(st),
                              _stream(stream))
+    _check(rc, st.as_dict())
+    return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
+
+
+def dyson_iterate_trunc(prob: Problem, S, J, src, max_radius, block_sites=None, tol=1e-12,
+                        max_iter=500, want_cols=False, want_nn=True, ws=None, out=None,
+                        stream=None):
+    """``dyson_iterate`` (FP64) restricted to the sites within ``max_radius`` of
+    each column's source."""
+    import torch
+    n_r, n_t = prob.n_r, prob.n_t
+    src = np.ascontiguousarray(np.asarray(src, dtype=np.int32).reshape(-1))
+    n_src = int(src.size)
+    block_sites = n_src if block_sites is None else int(block_sites)
+    _need(S, torch.complex128, (n_r, n_t, n_t), "S")
+    _need(J, torch.float64, (prob.n_real,), "J")
+    G_loc, G_nn, G_cols = _outputs(prob, n_src, S.device, out, want_cols, want_nn)
+    need = workspace_bytes(prob, n_src, block_sites, PREC_FP64)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=S.device)
+    st = Stats()
+    rc = lib().dyson_iterate_trunc(ctypes.byref(prob), _ptr(S), _ptr(J),
+                                   src.ctypes.data_as(_P(ctypes.c_int32)), n_src, block_sites,
+                                   int(max_radius), float(tol), int(max_iter), _ptr(G_cols),
+                                   _ptr(G_loc), _ptr(G_nn), _ptr(ws), ctypes.c_size_t(ws.numel()),
+                                   ctypes.byref(st), _stream(stream))
     _check(rc, st.as_dict())
     return {"G_loc": G_loc, "G_nn": G_nn, "G_cols": G_cols, "stats": st.as_dict(), "ws": ws}
 

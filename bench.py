@@ -61,8 +61,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline leg")
     ap.add_argument("--quick", action="store_true",
                     help="skip the time-to-solution and adjoint legs (profiling runs)")
-    ap.add_argument("--legs", default="fp64,mixed,sym,gmres,selfenergy,adjoint",
-                    help="comma list of extra legs: fp64, mixed, sym, gmres, selfenergy, adjoint")
+    ap.add_argument("--legs", default="fp64,mixed,sym,trunc,gmres,selfenergy,adjoint",
+                    help="comma list of extra legs: fp64, mixed, sym, trunc, gmres, selfenergy, "
+                         "adjoint")
     ap.add_argument("--gmres-restart", type=int, default=6)
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -303,6 +304,8 @@ def main():
                                "fraction_t0": float(frac[0]),
                                "fraction_t_end": float(frac[-1])}
     n_ref = n.clone()
+    ref_loc = outs["G_loc"].clone() if "trunc" in (set() if args.quick else
+                                                   set(args.legs.split(","))) else None
     tts = {}
     want = set() if args.quick else set(args.legs.split(","))
     legs = ()
@@ -317,10 +320,19 @@ def main():
         legs += (("fp64_pointgroup_tol1e-12", B.PREC_FP64, args.tol),
                  ("fp64_pointgroup_tol1e-9", B.PREC_FP64, 1e-9),
                  ("mixed_bf16x3_pointgroup_tol1e-9", B.PREC_BF16X3, 1e-9))
+    if "trunc" in want:
+        legs += (("fp64_trunc10_tol1e-12", B.PREC_FP64, args.tol),
+                 ("fp64_trunc14_tol1e-12", B.PREC_FP64, args.tol))
     for label, prec, tol in legs:
         # point-group legs: one source per C4v orbit (36 of 256), every G_ij kept
         sym = "pointgroup" in label
         solve = B.dyson_iterate_sym if sym else B.dyson_iterate
+        if "trunc" in label:
+            # far blocks truncated at a lattice distance from each source
+            radius = int(label.split("trunc")[1].split("_")[0])
+            solve = (lambda prob_, S_, J_, src_, radius=radius, **kw:
+                     B.dyson_iterate_trunc(prob_, S_, J_, src_, radius,
+                                           **{k: v for k, v in kw.items() if k != "prec"}))
         need = (B.sym_workspace_bytes(prob, src, block, prec) if sym
                 else B.workspace_bytes(prob, len(src), block, prec))
         ws_p = ws if (prec == B.PREC_FP64 and not sym) else torch.empty(
@@ -344,6 +356,10 @@ def main():
                       "tflops": round(st_p["gemm_flops"] / t_p / 1e12, 3)}
         if sym:
             tts[label]["sources_solved"] = orbit_count(wl.Lx, wl.Ly)
+        if "trunc" in label:
+            tts[label]["max_rel_dG_loc"] = (float((r["G_loc"] - ref_loc).abs().max() /
+                                                  ref_loc.abs().max()) if ref_loc is not None
+                                            else None)
     if "gmres" in want:
         tts.update(gmres_leg(B, prob, S, V, U, J, src, block, n_ref, args.gmres_restart))
     if "selfenergy" in want:

@@ -119,7 +119,7 @@ void gs_kernel(GsPass p) {
             for (int i = 0; i < KB; ++i) acc[i] += cmulc(v[i], x);
         }
         if (NORM) nrm += x.x * x.x + x.y * x.y;
-        if (WRITE && live) w[off] = x;
+        if (WRITE && live) __builtin_nontemporal_store(x, &w[off]);   // read back from HBM next pass
     }
     if (DOTS) {
 #pragma unroll

@@ -495,6 +495,9 @@ template <class E, int MODE>
 hipError_t launch_mode(const Geom& g, const SweepArgs& a, const void* St, const double2* S,
                        const int* src_blk, const void* X, void* out, const void* R,
                        double* partial, hipStream_t st) {
+    // An empty site set (the second colour of a lattice without bonds) is no
+    // launch at all: it writes nothing and leaves no partials.
+    if (a.n_sites * a.ntn == 0) return hipSuccess;
     dim3 grid(a.n_sites * a.ntn);
     typedef typename E::cplx cplx;
     const cplx* St_ = reinterpret_cast<const cplx*>(St);

@@ -372,6 +372,7 @@ hipError_t launch_bf3_operand(const Geom& g, const double2* St, void* out, hipSt
 hipError_t launch_correct_bf3(const Geom& g, const SweepArgs& a, const void* Abf,
                               const int* src_blk, const void* R32, const void* D32, void* Dn32,
                               double* partial, hipStream_t st) {
+    if (a.n_sites * a.ntn == 0) return hipSuccess;     // empty colour: nothing to update
     const dim3 grid(a.n_sites * a.ntn);
     const __bf16* A_ = reinterpret_cast<const __bf16*>(Abf);
     const fvec2* X_ = reinterpret_cast<const fvec2*>(D32);

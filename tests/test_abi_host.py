@@ -76,6 +76,10 @@ def test_dyson_iterate_rejects_bad_arguments_before_launch():
                          1, 1, 0, 0.0, 10, None, fake, None, fake, ctypes.c_size_t(1 << 40),
                          ctypes.byref(st), None)
     assert rc == B.SCD_EINVAL and "tol" in B.last_error()
+    rc = L.dyson_iterate(ctypes.byref(p), fake, fake, src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                         0, 1, 0, 1e-12, 10, None, fake, None, fake, ctypes.c_size_t(1 << 40),
+                         ctypes.byref(st), None)
+    assert rc == B.SCD_EINVAL and "n_src" in B.last_error()      # an empty source list
 
 
 def test_sigma_build_and_observables_reject_nulls():

@@ -59,7 +59,8 @@ def _solve(wl, device, sources, block_sites, want_cols=True, tol=1e-13, max_iter
     (W.custom(3, 5, 7, 5, J0=0.08, seed=4), 4),              # N_t = 19: padded tiles, ragged blocks
     (W.custom(4, 3, 6, 4, J0=0.1, periodic=True, seed=6), 5),
     (W.custom(5, 1, 9, 6, J0=0.12, seed=12), 2),
-], ids=["cfg1", "ragged3x5", "periodic4x3", "chain5"])
+    (W.custom(1, 1, 8, 4, J0=0.1, seed=2), 1),                # no bonds: G = S, empty second colour
+], ids=["cfg1", "ragged3x5", "periodic4x3", "chain5", "single_site"])
 def test_dyson_full_matches_dense_oracle(wl, block, device):
     c, S_ref, G = oracle_dense(wl)
     sources = list(range(wl.n_r))[::-1]                       # reversed order: block bookkeeping

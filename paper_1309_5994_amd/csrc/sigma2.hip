@@ -183,8 +183,10 @@ __device__ void site_phases(const double* U, double eps, Geom g, double* t1r, do
 // is one of four tabulated values (Theta_dn = Theta_up): e^{+-i Theta_1} for
 // 0 <-> 1 particle, e^{+-i (Theta_3 - Theta_1)} for 1 <-> 2 particles.  Six
 // key comparisons give the contour order's permutation, whose surviving
-// number-state paths come from the path table (LDS), so a path costs four
-// table reads and three complex products.  The tables are finite on the
+// number-state paths come from the path table (LDS).  Only three of the
+// comparisons involve d, so the inner loop over d keeps two running sums of
+// K(c, d) times the d factor and applies the paths once per stretch of
+// constant order (a few per (a, b, c)).  The tables are finite on the
 // imaginary branch (|eps|, |eps + U| times beta stay far from the double
 // range); the Boltzmann weight multiplies the product.
 __global__ __launch_bounds__(kS2Threads)
@@ -231,36 +233,64 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     if (e >= n_t * n_t) return;
     const int a = e / n_t, b = e - (e / n_t) * n_t;
     const double2* Ki = K + (size_t)site * n_t * n_t;
-    // keys of the written slots: later contour point first, a creation
-    // operator later than an annihilation operator at the same point
-    const int ka = 2 * a, kb = 2 * b + 1;
     double acc_r = 0.0, acc_i = 0.0;
-    for (int c = 0; c < n_t; ++c) {
-        const int kc = 2 * c + 1;
-        const int code_c = ((kc > ka) << 1) | ((kb > ka) << 2) | ((kb > kc) << 5);
-        for (int d = 0; d < n_t; ++d) {
-            const double2 k = Ki[(size_t)c * n_t + d];
-            const int kd = 2 * d;
-            const int code = code_c | (kd > ka) | ((kc > kd) << 3) | ((kb > kd) << 4);
-            const int p = tb.perm_of[code];
-            const int tpt[4] = {a, d, c, b};
-            double gr = 0.0, gi = 0.0;
+    // Surviving paths of contour order `code`, with the d-sums P1 = sum K(c, d)
+    // e^{-i T1}(d) and P3 = sum K(c, d) e^{-i (T3 - T1)}(d) over a stretch of d
+    // on which that order holds (the operator at d annihilates: table 1 or 3).
+    auto flush = [&](int c, int code, double2 P1, double2 P3) {
+        const int p = tb.perm_of[code];
 #pragma unroll
-            for (int s1 = 0; s1 < 2; ++s1) {
-                const int np = tb.npath[p][s1];
-                for (int q = 0; q < np; ++q) {
-                    const signed char* tq = tb.tab[p][s1][q];
-                    double2 f = cmul2(fac[tq[0]][tpt[0]], fac[tq[1]][tpt[1]]);
-                    f = cmul2(f, fac[tq[2]][tpt[2]]);
-                    f = cmul2(f, fac[tq[3]][tpt[3]]);
-                    const double w = tb.amp[p][s1][q] * pw[tb.nu[p][s1][q]];
-                    gr += w * f.x;
-                    gi += w * f.y;
-                }
+        for (int s1 = 0; s1 < 2; ++s1) {
+            const int np = tb.npath[p][s1];
+            for (int q = 0; q < np; ++q) {
+                const signed char* tq = tb.tab[p][s1][q];
+                double2 f = cmul2(fac[tq[0]][a], fac[tq[2]][c]);
+                f = cmul2(f, fac[tq[3]][b]);
+                f = cmul2(f, tq[1] == 1 ? P1 : P3);
+                // G^II carries (-i)^2 = -1, so part = - K G^II adds + w f
+                const double w = tb.amp[p][s1][q] * pw[tb.nu[p][s1][q]];
+                acc_r += w * f.x;
+                acc_i += w * f.y;
             }
-            // G^II carries (-i)^2 = -1; part = - K G^II = + K (gr + i gi)
-            acc_r += k.x * gr - k.y * gi;
-            acc_i += k.x * gi + k.y * gr;
+        }
+    };
+    // With (a, b, c) fixed the contour order depends on d only through
+    // d > a, d <= c and d <= b (keys: later contour point first, a creation
+    // operator later than an annihilation operator at the same point), so the
+    // d-sums run over stretches cut after d = a and d = c (nearly uniform over
+    // a wave), each split at the lane's own b by a snapshot of the running sums.
+    for (int c = 0; c < n_t; ++c) {
+        // the pairs without d: (a, c) c >= a, (a, b) b >= a, (c, b) c < b
+        const int code_c = ((c >= a) << 1) | ((b >= a) << 2) | ((c < b) << 5);
+        const double2* Kc = Ki + (size_t)c * n_t;
+        double2 s1 = make_double2(0.0, 0.0), s3 = s1, n1 = s1, n3 = s1;
+        int lo = 0;
+        for (int d = 0; d < n_t; ++d) {
+            const double2 k = Kc[d];
+            const double2 u1 = cmul2(k, fac[1][d]), u3 = cmul2(k, fac[3][d]);
+            s1.x += u1.x;
+            s1.y += u1.y;
+            s3.x += u3.x;
+            s3.y += u3.y;
+            if (d == b) {
+                n1 = s1;
+                n3 = s3;
+            }
+            if (d == a || d == c || d == n_t - 1) {
+                // stretch [lo, d]: d > a and d <= c are constant on it
+                const int base = code_c | (lo > a) | ((c >= lo) << 3);
+                if (b >= lo)                     // d' <= b: [lo, min(b, d)]
+                    flush(c, base | (1 << 4), b < d ? n1 : s1, b < d ? n3 : s3);
+                if (b < d) {                     // d' > b: [max(lo, b + 1), d]
+                    const bool split = b >= lo;
+                    flush(c, base,
+                          split ? make_double2(s1.x - n1.x, s1.y - n1.y) : s1,
+                          split ? make_double2(s3.x - n3.x, s3.y - n3.y) : s3);
+                }
+                s1 = make_double2(0.0, 0.0);
+                s3 = s1;
+                lo = d + 1;
+            }
         }
     }
     out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);

@@ -136,6 +136,37 @@ def sigma_tilde(V, U_real, mu, J_real, c: Contour, Lx: int, Ly: int, periodic: b
     return out
 
 
+def sigma_tilde_entries(V, U_real, mu, J_real, c: Contour, Lx: int, Ly: int, periodic: bool,
+                        G_loc: np.ndarray, entries) -> np.ndarray:
+    """Sigma~_i(a, b) of eq. defnSigmatilde at the listed (i, a, b) only: the
+    same contraction as sigma_tilde, restricted to those outputs, for contour
+    lengths where the whole N_t^4 table does not fit in memory."""
+    U_real = np.asarray(U_real, dtype=np.float64)
+    eps = np.asarray(V, dtype=np.float64) - 0.5 * U_real[0] - mu
+    nbr = neighbours(Lx, Ly, periodic)
+    wJ = c.w * hopping_on_contour(J_real, c)
+    n = c.n_t
+    cc, dd = (x.ravel() for x in np.meshgrid(np.arange(n), np.arange(n), indexing="ij"))
+    out = []
+    for i, a, b in entries:
+        K = np.zeros((n, n), dtype=complex)
+        for k in nbr[i]:
+            if k >= 0:
+                K += G_loc[k]
+        K = wJ[:, None] * K * wJ[None, :]
+        S1 = atomic_gf(eps[i], U_real, c)
+        # G~(a, d; c, b) for all (c, d): operator points (a1, a2, b1, b2) = (a, d, c, b)
+        idx = np.stack([np.full(n * n, a), dd, cc, np.full(n * n, b)], axis=1)
+        Gt = np.zeros(n * n, dtype=complex)
+        for s2 in ("up", "dn"):
+            Gt += two_particle_gf(eps[i], U_real, c, "up", s2, idx)
+            Gt -= S1[a, b] * S1[dd, cc]                        # - G(a1, b2) G(a2, b1)
+            if s2 == "up":
+                Gt += S1[a, cc] * S1[dd, b]                    # + G(a1, b1) G(a2, b2)
+        out.append(-np.sum(Gt * K[cc, dd]))
+    return np.array(out)
+
+
 def dressed_blocks(S: np.ndarray, Sig_t: np.ndarray) -> np.ndarray:
     """B_i^-1 (contour inverse) = S_i (S_i - Sigma~_i)^-1 S_i per site."""
     return np.stack([S[i] @ np.linalg.solve(S[i] - Sig_t[i], S[i]) for i in range(S.shape[0])])

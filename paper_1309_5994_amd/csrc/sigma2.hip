@@ -184,9 +184,10 @@ __device__ void site_phases(const double* U, double eps, Geom g, double* t1r, do
 // 0 <-> 1 particle, e^{+-i (Theta_3 - Theta_1)} for 1 <-> 2 particles.  Six
 // key comparisons give the contour order's permutation, whose surviving
 // number-state paths come from the path table (LDS).  Only three of the
-// comparisons involve d, so the inner loop over d keeps two running sums of
-// K(c, d) times the d factor and applies the paths once per stretch of
-// constant order (a few per (a, b, c)).  The tables are finite on the
+// comparisons involve d, so per contour index c the workgroup stages the
+// prefix sums over d of K(c, d) times the d factors, and each output applies
+// the paths once per stretch of constant order (at most four per (a, b, c)).
+// The tables are finite on the
 // imaginary branch (|eps|, |eps + U| times beta stay far from the double
 // range); the Boltzmann weight multiplies the product.
 __global__ __launch_bounds__(kS2Threads)
@@ -197,6 +198,10 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     __shared__ double cum[kMaxNt];
     __shared__ double2 fac[4][kMaxNt];   // [0] e^{i T1}, [1] e^{-i T1}, [2] e^{i(T3-T1)}, [3] e^{-i(T3-T1)}
     __shared__ PathTable tb;
+    // Prefix sums over d of row c: pz[0] + i pz[1] = sum_{d' < d} K(c, d')
+    // e^{-i T1}(d'), pz[2] + i pz[3] the same with e^{-i (T3 - T1)}(d');
+    // pz[.][0] = 0.
+    __shared__ double pz[4][kMaxNt + 1];
     {
         const signed char* src = reinterpret_cast<const signed char*>(&paths);
         signed char* dst = reinterpret_cast<signed char*>(&tb);
@@ -229,9 +234,13 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     const double lz = mx + log(exp(-mx) + 2.0 * exp(lw1 - mx) + exp(lw3 - mx));
     const double pw[4] = {exp(-lz), exp(lw1 - lz), exp(lw1 - lz), exp(lw3 - lz)};
 
+    // Every thread takes part in staging the rows (barriers below); threads
+    // past the last output only stage.
     const int e = blockIdx.x * kS2Threads + threadIdx.x;
-    if (e >= n_t * n_t) return;
-    const int a = e / n_t, b = e - (e / n_t) * n_t;
+    const bool live = e < n_t * n_t;
+    const int ec = live ? e : 0;
+    const int a = ec / n_t, b = ec - (ec / n_t) * n_t;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double2* Ki = K + (size_t)site * n_t * n_t;
     double acc_r = 0.0, acc_i = 0.0;
     // Surviving paths of contour order `code`, with the d-sums P1 = sum K(c, d)
@@ -256,44 +265,68 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
     };
     // With (a, b, c) fixed the contour order depends on d only through
     // d > a, d <= c and d <= b (keys: later contour point first, a creation
-    // operator later than an annihilation operator at the same point), so the
-    // d-sums run over stretches cut after d = a and d = c (nearly uniform over
-    // a wave), each split at the lane's own b by a snapshot of the running sums.
+    // operator later than an annihilation operator at the same point): the
+    // cuts after d = a, b and c split [0, N_t) into at most four stretches of
+    // constant order, and each stretch's d-sums are differences of the row's
+    // prefix sums.  O(N_t^3) per site.
     for (int c = 0; c < n_t; ++c) {
-        // the pairs without d: (a, c) c >= a, (a, b) b >= a, (c, b) c < b
-        const int code_c = ((c >= a) << 1) | ((b >= a) << 2) | ((c < b) << 5);
-        const double2* Kc = Ki + (size_t)c * n_t;
-        double2 s1 = make_double2(0.0, 0.0), s3 = s1, n1 = s1, n3 = s1;
-        int lo = 0;
-        for (int d = 0; d < n_t; ++d) {
-            const double2 k = Kc[d];
-            const double2 u1 = cmul2(k, fac[1][d]), u3 = cmul2(k, fac[3][d]);
-            s1.x += u1.x;
-            s1.y += u1.y;
-            s3.x += u3.x;
-            s3.y += u3.y;
-            if (d == b) {
-                n1 = s1;
-                n3 = s3;
+        // Row c times the d factors, one element per thread (N_t <= 256).
+        {
+            const int d = tid;
+            double2 u1 = make_double2(0.0, 0.0), u3 = u1;
+            if (d < n_t) {
+                const double2 k = Ki[(size_t)c * n_t + d];
+                u1 = cmul2(k, fac[1][d]);
+                u3 = cmul2(k, fac[3][d]);
             }
-            if (d == a || d == c || d == n_t - 1) {
-                // stretch [lo, d]: d > a and d <= c are constant on it
-                const int base = code_c | (lo > a) | ((c >= lo) << 3);
-                if (b >= lo)                     // d' <= b: [lo, min(b, d)]
-                    flush(c, base | (1 << 4), b < d ? n1 : s1, b < d ? n3 : s3);
-                if (b < d) {                     // d' > b: [max(lo, b + 1), d]
-                    const bool split = b >= lo;
-                    flush(c, base,
-                          split ? make_double2(s1.x - n1.x, s1.y - n1.y) : s1,
-                          split ? make_double2(s3.x - n3.x, s3.y - n3.y) : s3);
+            __syncthreads();              // the previous row's sums are no longer read
+            pz[0][d + 1] = u1.x;
+            pz[1][d + 1] = u1.y;
+            pz[2][d + 1] = u3.x;
+            pz[3][d + 1] = u3.y;
+            if (d < 4) pz[d][0] = 0.0;
+        }
+        __syncthreads();
+        // Inclusive scans: wave w scans array w in chunks of 64 with a carry.
+        {
+            double carry = 0.0;
+            for (int c0 = 0; c0 < n_t; c0 += 64) {
+                double v = pz[wave][c0 + lane + 1];
+#pragma unroll
+                for (int k = 1; k < 64; k <<= 1) {
+                    const double t = __shfl_up(v, k);
+                    if (lane >= k) v += t;
                 }
-                s1 = make_double2(0.0, 0.0);
-                s3 = s1;
-                lo = d + 1;
+                v += carry;
+                pz[wave][c0 + lane + 1] = v;
+                carry = __shfl(v, 63);
+            }
+        }
+        __syncthreads();
+        if (live) {
+            // the pairs without d: (a, c) c >= a, (a, b) b >= a, (c, b) c < b
+            const int code_c = ((c >= a) << 1) | ((b >= a) << 2) | ((c < b) << 5);
+            // cut points in increasing order (a stretch ends at each)
+            int h0 = a, h1 = b, h2 = c;
+            if (h0 > h1) { const int t = h0; h0 = h1; h1 = t; }
+            if (h1 > h2) { const int t = h1; h1 = h2; h2 = t; }
+            if (h0 > h1) { const int t = h0; h0 = h1; h1 = t; }
+            const int hs[4] = {h0, h1, h2, n_t - 1};
+            int lo = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int h = hs[k];
+                if (h < lo) continue;     // repeated cut
+                // stretch [lo, h]: d > a, d <= c and d <= b are constant on it
+                const int code = code_c | (lo > a) | ((c >= lo) << 3) | ((b >= lo) << 4);
+                const double2 P1 = make_double2(pz[0][h + 1] - pz[0][lo], pz[1][h + 1] - pz[1][lo]);
+                const double2 P3 = make_double2(pz[2][h + 1] - pz[2][lo], pz[3][h + 1] - pz[3][lo]);
+                flush(c, code, P1, P3);
+                lo = h + 1;
             }
         }
     }
-    out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);
+    if (live) out[(size_t)site * n_t * n_t + e] = make_double2(acc_r, acc_i);
 }
 
 // M = K S per site (one thread per (c, b)), the first factor of the

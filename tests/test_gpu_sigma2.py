@@ -45,6 +45,36 @@ def test_sigma2_matches_oracle(wl, device):
     assert np.abs(got - ref).max() <= 1e-12 * scale
 
 
+@pytest.mark.parametrize("wl", [
+    _modulated(W.custom(3, 3, 64, 16, J0=0.08, seed=7)),                    # N_t = 144, U(t)
+    W.custom(3, 3, 120, 16, J0=0.06, periodic=True, seed=9),                # N_t = 256 (largest)
+], ids=["3x3_nt144_mod", "periodic3x3_nt256"])
+def test_sigma2_long_contour_sampled_entries(wl, device):
+    # Contours longer than one 64-wide scan chunk, against the oracle's
+    # contraction at sampled outputs (corners of the contour grid included),
+    # from a seeded arbitrary G_loc.
+    import torch
+    from paper_1309_5994_amd import scdyson as B
+    c = O.make_contour(wl.n_real, wl.n_imag, wl.dt, wl.beta, wl.t_min)
+    n_t = c.n_t
+    rng = np.random.default_rng(wl.n_real)
+    G_loc = 0.3 * (rng.standard_normal((wl.n_r, n_t, n_t)) + 1j * rng.standard_normal((wl.n_r, n_t, n_t)))
+    prob, V, U, J = gpu_inputs(wl, device)
+    S = B.sigma_build(prob, V, U)
+    got = _np(B.sigma2_build(prob, V, U, J, S, torch.as_tensor(G_loc, device=device)))
+    last = n_t - 1
+    entries = [(0, 0, 0), (4, last, last), (8, 0, last), (4, last, 0),
+               (2, wl.n_real - 1, wl.n_real), (6, 2 * wl.n_real, 3)]
+    entries += [(int(i), int(a), int(b)) for i, a, b in
+                zip(rng.integers(0, wl.n_r, 10), rng.integers(0, n_t, 10), rng.integers(0, n_t, 10))]
+    ref = SE.sigma_tilde_entries(wl.V, wl.U, wl.mu, wl.J, c, wl.Lx, wl.Ly, wl.periodic, G_loc,
+                                 entries)
+    mine = np.array([got[i, a, b] for i, a, b in entries])
+    scale = np.abs(ref).max()
+    assert scale > 1e-6
+    assert np.abs(mine - ref).max() <= 1e-12 * scale
+
+
 def test_sigma2_dress_matches_oracle(device):
     import torch
     from paper_1309_5994_amd import scdyson as B

@@ -8,6 +8,7 @@ eq. defnSigmatilde, eq. Sigmamix).
   (products and ratios of the tabulated zeta_nu) is reproduced.
 * The dressed block S (S - Sigma~)^-1 S equals the contour-algebra inverse of
   calG^-1 - calG^-1 o Sigma~ o calG^-1 built with explicit weights.
+* The contraction restricted to listed outputs equals the whole table's entries.
 * J = 0 gives Sigma~ = 0; Sigma~ scales as J^2 at small J; the mixed
   self-consistency loop converges and its fixed point satisfies the
   self-consistency equation.
@@ -77,6 +78,22 @@ def test_sigma_tilde_zero_hopping_and_j_squared_scaling():
     assert np.abs(_sigma(0.0)).max() == 0.0
     a, b = np.abs(_sigma(0.02)).max(), np.abs(_sigma(0.01)).max()
     assert 3.8 < a / b < 4.2
+
+
+def test_sigma_tilde_entries_restrict_the_full_contraction():
+    # the sampled form (for long contours) against the whole table, with a
+    # time-dependent U and an arbitrary (non-lattice) G_loc
+    c = _contour()
+    rng = np.random.default_rng(4)
+    V = np.array([0.05, -0.1, 0.0, 0.12])
+    U = 1.0 + 0.2 * np.sin(np.arange(c.n_real))
+    J = np.full(c.n_real, 0.08)
+    G_loc = 0.3 * (rng.standard_normal((4, c.n_t, c.n_t)) + 1j * rng.standard_normal((4, c.n_t, c.n_t)))
+    full = SE.sigma_tilde(V, U, 0.1, J, c, 2, 2, False, G_loc)
+    entries = [(0, 0, 0), (1, 3, 11), (2, c.n_t - 1, 0), (3, 7, 7), (1, 12, 2)]
+    got = SE.sigma_tilde_entries(V, U, 0.1, J, c, 2, 2, False, G_loc, entries)
+    ref = np.array([full[i, a, b] for i, a, b in entries])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(full).max()
 
 
 def test_selfconsistent_loop_converges_to_a_fixed_point():

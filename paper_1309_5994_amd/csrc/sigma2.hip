@@ -33,6 +33,7 @@ namespace scd {
 namespace {
 
 constexpr int kS2Threads = 256;
+constexpr int kDressThreads = 1024;   // one workgroup per site: 16 waves to hide memory latency
 
 __device__ inline double2 cmul2(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -396,12 +397,12 @@ void sigma2_onebody_kernel(const double2* __restrict__ S, const double2* __restr
 // S' = S (S - Sigma~)^-1 S per site: Gauss-Jordan elimination with partial
 // pivoting of [S - Sigma~ | S] (one workgroup per site, the augmented matrix
 // in the workspace), then the product with S.
-__global__ __launch_bounds__(kS2Threads)
+__global__ __launch_bounds__(kDressThreads)
 void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig,
                   double2* __restrict__ aug, double2* __restrict__ S_out, Geom g,
                   int* __restrict__ singular) {
-    __shared__ double rmax[kS2Threads];
-    __shared__ int ridx[kS2Threads];
+    __shared__ double rmax[kDressThreads];
+    __shared__ int ridx[kDressThreads];
     __shared__ int piv_s;
     const int site = blockIdx.x;
     const int n = g.n_t, w = 2 * n;
@@ -409,7 +410,7 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
     const double2* Si = S + (size_t)site * per;
     const double2* Gi = sig + (size_t)site * per;
     double2* A = aug + (size_t)site * n * w;                 // [n][2n]
-    for (int e = threadIdx.x; e < n * w; e += kS2Threads) {
+    for (int e = threadIdx.x; e < n * w; e += kDressThreads) {
         const int r = e / w, c = e - (e / w) * w;
         if (c < n) {
             const double2 s = Si[(size_t)r * n + c], x = Gi[(size_t)r * n + c];
@@ -423,7 +424,7 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
         // pivot: largest |A(r, k)| for r >= k
         double best = -1.0;
         int bi = k;
-        for (int r = k + threadIdx.x; r < n; r += kS2Threads) {
+        for (int r = k + threadIdx.x; r < n; r += kDressThreads) {
             const double2 v = A[(size_t)r * w + k];
             const double m = fabs(v.x) + fabs(v.y);
             if (m > best) {
@@ -434,7 +435,7 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
         rmax[threadIdx.x] = best;
         ridx[threadIdx.x] = bi;
         __syncthreads();
-        for (int s = kS2Threads / 2; s > 0; s >>= 1) {
+        for (int s = kDressThreads / 2; s > 0; s >>= 1) {
             if ((int)threadIdx.x < s && rmax[threadIdx.x + s] > rmax[threadIdx.x]) {
                 rmax[threadIdx.x] = rmax[threadIdx.x + s];
                 ridx[threadIdx.x] = ridx[threadIdx.x + s];
@@ -448,7 +449,7 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
         __syncthreads();
         const int p = piv_s;
         if (p != k)
-            for (int c = threadIdx.x; c < w; c += kS2Threads) {
+            for (int c = threadIdx.x; c < w; c += kDressThreads) {
                 const double2 t = A[(size_t)k * w + c];
                 A[(size_t)k * w + c] = A[(size_t)p * w + c];
                 A[(size_t)p * w + c] = t;
@@ -459,24 +460,27 @@ void dress_kernel(const double2* __restrict__ S, const double2* __restrict__ sig
         const double den = pv.x * pv.x + pv.y * pv.y;
         const double2 inv = den > 0.0 ? make_double2(pv.x / den, -pv.y / den) : make_double2(0, 0);
         __syncthreads();
-        for (int c = threadIdx.x; c < w; c += kS2Threads)
+        for (int c = threadIdx.x; c < w; c += kDressThreads)
             A[(size_t)k * w + c] = cmul2(A[(size_t)k * w + c], inv);
         __syncthreads();
-        // eliminate column k from every other row
-        for (int e = threadIdx.x; e < n * w; e += kS2Threads) {
-            const int r = e / w, c = e - (e / w) * w;
-            if (r == k || c == k) continue;
+        // eliminate column k from every other row; columns left of k are
+        // already zero in the pivot row
+        const int wk = w - k - 1;
+        for (int e = threadIdx.x; e < n * wk; e += kDressThreads) {
+            const int r = e / wk, c = k + 1 + (e - (e / wk) * wk);
+            if (r == k) continue;
             const double2 f = A[(size_t)r * w + k];
             const double2 v = cmul2(f, A[(size_t)k * w + c]);
-            A[e] = make_double2(A[e].x - v.x, A[e].y - v.y);
+            const double2 o = A[(size_t)r * w + c];
+            A[(size_t)r * w + c] = make_double2(o.x - v.x, o.y - v.y);
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < n; r += kS2Threads)
+        for (int r = threadIdx.x; r < n; r += kDressThreads)
             if (r != k) A[(size_t)r * w + k] = make_double2(0.0, 0.0);
         __syncthreads();
     }
     // S' = S Y, Y = right half of A
-    for (int e = threadIdx.x; e < n * n; e += kS2Threads) {
+    for (int e = threadIdx.x; e < n * n; e += kDressThreads) {
         const int r = e / n, c = e - (e / n) * n;
         double2 acc = make_double2(0.0, 0.0);
         for (int q = 0; q < n; ++q) {
@@ -544,7 +548,7 @@ hipError_t launch_sigma2(const Geom& g, const double* V, const double* U, const 
 
 hipError_t launch_dress(const Geom& g, const double2* S, const double2* sig, double2* aug,
                         double2* S_out, int* singular, hipStream_t st) {
-    hipLaunchKernelGGL(dress_kernel, dim3(g.n_r), dim3(kS2Threads), 0, st, S, sig, aug, S_out, g,
+    hipLaunchKernelGGL(dress_kernel, dim3(g.n_r), dim3(kDressThreads), 0, st, S, sig, aug, S_out, g,
                        singular);
     return hipGetLastError();
 }

@@ -11,15 +11,17 @@
 //   Sigma~ = - sum_{c,d} K(c,d) [G^II_{up up} + G^II_{up dn}](a, d; c, b)
 //            + 2 S(a,b) sum_{c,d} K(c,d) S(d,c) - sum_{c,d} S(a,c) K(c,d) S(d,b),
 //
-// so only the two-particle part needs the N_t^4 sum.  G^II is evaluated on the
-// fly in the number basis |0>, |dn>, |up>, |up dn> (eq. cumulanttabulation):
-// the four operators c_up(a) c_s1(d) c^dag_s1(c) c^dag_up(b) are put in contour
-// order (later first; at one contour index creation operators count as later,
+// so only the two-particle part is a sum over (c, d).  G^II is evaluated in
+// the number basis |0>, |dn>, |up>, |up dn> (eq. cumulanttabulation): the four
+// operators c_up(a) c_s1(d) c^dag_s1(c) c^dag_up(b) are put in contour order
+// (later first; at one contour index creation operators count as later,
 // operators of one kind keep their written order) with the permutation's sign,
 // and every initial state is carried through the ordered product, each
 // operator contributing exp(i Theta_after(z) - i Theta_before(z)); the phases
 // and the Boltzmann weight are combined in one exponent, so imaginary-branch
-// factors never overflow.
+// factors never overflow.  Each path is a product of single-time factors and
+// the order changes with d only at d = a, b, c, so the d-sum is a difference
+// of prefix sums and the contraction costs O(N_t^3) per site.
 //
 // The dressed block (the contour inverse of calG^-1 - Sigma, with
 // Sigma = calG^-1 o Sigma~ o calG^-1) is S' = S (S - Sigma~)^-1 S in plain

@@ -231,27 +231,30 @@ void to_f32_kernel(const dvec2* __restrict__ in, fvec2* __restrict__ out, size_t
     }
 }
 
-// X += D: the FP64 iterate absorbs the low-precision correction; four
-// elements per thread and step (16-byte accesses, more bytes in flight).
+// X += D: the FP64 iterate absorbs the low-precision correction.  Each thread
+// takes four elements a workgroup-width apart (every load and store of a wave
+// is one contiguous run), all loads issued before the adds; nontemporal,
+// since each byte is touched once.
 __global__ __launch_bounds__(256)
 void axpy_kernel(dvec2* __restrict__ X, const fvec2* __restrict__ D, size_t n) {
-    const size_t n4 = n / 4;
-    const fvec4* D4 = reinterpret_cast<const fvec4*>(D);
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n4;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const fvec4 d0 = D4[2 * e], d1 = D4[2 * e + 1];
-        dvec2* x = X + 4 * e;
-        const dvec2 x0 = x[0], x1 = x[1], x2 = x[2], x3 = x[3];
-        x[0] = x0 + dvec2{(double)d0.x, (double)d0.y};
-        x[1] = x1 + dvec2{(double)d0.z, (double)d0.w};
-        x[2] = x2 + dvec2{(double)d1.x, (double)d1.y};
-        x[3] = x3 + dvec2{(double)d1.z, (double)d1.w};
-    }
-    // tail (n not a multiple of 4)
-    for (size_t e = 4 * n4 + (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const fvec2 d = D[e];
-        X[e] += dvec2{(double)d.x, (double)d.y};
+    const size_t span = 4 * (size_t)blockDim.x;
+    for (size_t b = (size_t)blockIdx.x * span; b < n; b += (size_t)gridDim.x * span) {
+        dvec2 x[4];
+        fvec2 d[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const size_t e = b + (size_t)k * blockDim.x + threadIdx.x;
+            if (e < n) {
+                x[k] = __builtin_nontemporal_load(&X[e]);
+                d[k] = __builtin_nontemporal_load(&D[e]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const size_t e = b + (size_t)k * blockDim.x + threadIdx.x;
+            if (e < n)
+                __builtin_nontemporal_store(x[k] + dvec2{(double)d[k].x, (double)d[k].y}, &X[e]);
+        }
     }
 }
 

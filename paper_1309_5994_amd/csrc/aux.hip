@@ -61,27 +61,29 @@ __global__ __launch_bounds__(256)
 void init_block_kernel(const double2* __restrict__ S, const int* __restrict__ src_blk, int bs,
                        int ldx, int x0_kind, int x0_fixed, double2* __restrict__ X,
                        double2* __restrict__ Xn, Geom g) {
-    const size_t total = (size_t)g.n_r * g.mp * ldx;
+    // One row (target site i, contour index a) at a time, its columns across
+    // the threads (coalesced, 32-bit index arithmetic).
     const int cps = x0_kind == X0_BLOCK ? g.n_t : 1;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int col = (int)(e % ldx);
-        const size_t r = e / ldx;
-        const int a = (int)(r % g.mp);
-        const int i = (int)(r / g.mp);
-        double2 v = make_double2(0.0, 0.0);
-        const int s = col / cps;
-        if (s < bs && a < g.n_t && src_blk[s] == i) {
-            const double2* Si = S + (size_t)i * g.n_t * g.n_t;
-            if (x0_kind == X0_COL_T)
-                v = Si[(size_t)x0_fixed * g.n_t + a];
-            else if (x0_kind == X0_COL)
-                v = Si[(size_t)a * g.n_t + x0_fixed];
-            else
-                v = Si[(size_t)a * g.n_t + (col - s * g.n_t)];
+    const int rows = g.n_r * g.mp;
+    for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int i = r / g.mp, a = r - (r / g.mp) * g.mp;
+        const double2* Si = S + (size_t)i * g.n_t * g.n_t;
+        dvec2* Xr = reinterpret_cast<dvec2*>(X) + (size_t)r * ldx;
+        dvec2* Xnr = Xn ? reinterpret_cast<dvec2*>(Xn) + (size_t)r * ldx : nullptr;
+        for (int col = threadIdx.x; col < ldx; col += blockDim.x) {
+            double2 v = make_double2(0.0, 0.0);
+            const int s = col / cps;
+            if (a < g.n_t && s < bs && src_blk[s] == i) {
+                if (x0_kind == X0_COL_T)
+                    v = Si[(size_t)x0_fixed * g.n_t + a];
+                else if (x0_kind == X0_COL)
+                    v = Si[(size_t)a * g.n_t + x0_fixed];
+                else
+                    v = Si[(size_t)a * g.n_t + (col - s * cps)];
+            }
+            __builtin_nontemporal_store(dvec2{v.x, v.y}, &Xr[col]);
+            if (Xnr) __builtin_nontemporal_store(dvec2{0.0, 0.0}, &Xnr[col]);
         }
-        X[e] = v;
-        if (Xn) Xn[e] = make_double2(0.0, 0.0);
     }
 }
 

@@ -239,6 +239,8 @@ void sigma2_pair_kernel(const double2* __restrict__ K, const double* __restrict_
 
     // Every thread takes part in staging the rows (barriers below); threads
     // past the last output only stage.
+    static_assert(kS2Threads == 4 * 64, "one wave per scanned array");
+    static_assert(kMaxNt <= kS2Threads, "one row element per thread");
     const int e = blockIdx.x * kS2Threads + threadIdx.x;
     const bool live = e < n_t * n_t;
     const int ec = live ? e : 0;

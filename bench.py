@@ -215,8 +215,8 @@ def adjoint_leg(B, prob, S, V, U, J, wl, forward_full_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(column blocks shard over GPUs, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(the column blocks would shard over GPUs)"}))
         sys.exit(2)
     import torch
     from paper_1309_5994_amd import scdyson as B

@@ -38,7 +38,7 @@ something other than itself: the Fock-space trace, contour normalisation and
 KMS identities, the J=0 and two-site closed forms, the per-momentum solution of
 translation-invariant lattices, the U=0 free-fermion propagator (which fixes
 the contour conventions), C4v symmetry and the Dyson-series light cone.
-Readings of the paper where it is silent are listed in the design doc.
+Where the paper is silent, each module states the reading it takes.
 """
 from .contour import Contour, make_contour
 from .atomic import atomic_gf, atomic_gf_fock, boltzmann_weights, level_phases

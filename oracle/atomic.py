@@ -24,7 +24,7 @@ Two independent evaluations:
   and the evolution operators multiplied out for each contour ordering.  It is
   the pin for the closed form.
 
-Readings: the phase integral of U(t) is a cumulative trapezoid on
+Readings (the paper is silent here): the phase integral of U(t) is a cumulative trapezoid on
 the forward grid, backward points copy their forward partner, and imaginary
 points use E(t_min) times the complex time elapsed since t_min.
 """

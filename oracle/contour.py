@@ -6,7 +6,7 @@ runs forward to t_max, back to t_min, and then down the imaginary axis to
 t_min - i beta, where the thermal initial state lives.  N_t = 2 N_real + N_imag.
 
 The paper does not fix where the points sit or which quadrature is used; this
-module takes the following reading (also listed in the design doc):
+module takes the following reading:
 
 * forward  a in [0, N_real):          z_a = t_min + a dt,              w_a = +dt
 * backward a in [N_real, 2 N_real):   z_a = t_min + (2N_real-1-a) dt,   w_a = -dt

@@ -12,7 +12,7 @@ need Lx, Ly >= 3 so that no bond is listed twice.
 
 The hopping is uniform in space and given per forward time; the backward
 branch uses the forward value at the same physical time and the imaginary
-branch uses J(t_min) (reading listed in the design doc).
+branch uses J(t_min) (a reading: the paper does not say).
 """
 import numpy as np
 
